@@ -1,0 +1,196 @@
+/*
+ * lrhe.h -- C ABI of the MI355X (gfx950) library for privacy-preserving
+ * logistic-regression inference under BFV, after "Scalable privacy-preserving
+ * cancer type prediction with homomorphic encryption" (arXiv 2204.05496).
+ *
+ * Parties and calls follow the paper's private inference protocol (section
+ * "Private inference protocol"): the client generates keys, encodes and
+ * encrypts its |X| x f feature matrix (n features per polynomial), the server
+ * encodes W^T (|Y| x ceil(f/n) plaintexts) and the all-slot biases, computes
+ * Y^ = X^ x W- + B- with the fast matrix multiplication of Algorithm 1
+ * (section "Matrix multiplication algorithm"), and the client decrypts and
+ * decodes the class scores, whose argmax is the predicted class (section
+ * "Approximation of non-linear function in private inference").  The standard
+ * encrypted matrix multiplication the paper compares against (section
+ * "Comparison to standard LR") is provided as the baseline.
+ *
+ * Conventions (the paper runs on SEAL and leaves them implicit):
+ *   - ring R = Z[X]/(X^n + 1); data primes q_0..q_{L-1} and one special prime
+ *     P, each < 2^30 and = 1 mod 2n; plaintext modulus t prime, = 1 mod 2n.
+ *   - slot j of a plaintext is its evaluation at psi_t^(e_j), e_j = 3^j for
+ *     j < n/2 and -3^(j-n/2) otherwise (mod 2n); psi_t = g^((t-1)/2n) with g
+ *     the smallest generator of Z_t^*.  Plaintext polynomials are lifted to
+ *     the ciphertext moduli by their centred representative.
+ *   - encryption ct = ([pk0 u + e0 + round(Q m / t)]_Q, [pk1 u + e1]_Q), u
+ *     ternary, e0, e1 centred binomial (eta = 21), all drawn from ChaCha20
+ *     (RFC 8439) streams: key = seed, nonce = (kind, id); see DESIGN notes.
+ *   - the rotate-and-accumulate loop of Algorithm 1 uses the Galois elements
+ *     3^(n/4), 3^(n/8), ..., 3, then 2n-1 (row swap): log2 n rotations.
+ *   - key switching: RNS digits [d]_{q_i}, one special prime P, rounded
+ *     division by P.
+ *   - bias: the all-slot plaintext b_j is added after the rotate-and-sum and
+ *     before the one-hot mask; result r = i |Y| + j of Algorithm 1 lands in
+ *     output ciphertext r / n, slot r mod n.
+ *
+ * Memory: keys and models are allocated by the library on the context's
+ * device and freed by their destroy call.  Ciphertext matrices, feature and
+ * weight inputs and workspaces are caller-owned device buffers (for example
+ * torch tensors); their sizes come from lrhe_ctx_info / lrhe_workspace_bytes.
+ * Ciphertexts on the device are uint32 [2][L][n] per ciphertext, evaluation
+ * (NTT) form, residues in [0, q_i).  The secret key never leaves the host.
+ * Streams are hipStream_t passed as void* (NULL = the default stream); every
+ * call is asynchronous on its stream unless it returns host data.
+ *
+ * Errors: every int-returning call returns LRHE_OK (0) or a negative code;
+ * lrhe_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef LRHE_H
+#define LRHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LRHE_OK = 0,
+  LRHE_EINVAL = -1,   /* bad argument, shape or handle */
+  LRHE_EPARAM = -2,   /* parameters rejected (primality, congruence, size, security bound) */
+  LRHE_ENOMEM = -3,   /* device allocation failed or workspace too small */
+  LRHE_EAGAIN = -4,   /* server admission refused: over the memory budget */
+  LRHE_EDEVICE = -5,  /* HIP runtime error */
+  LRHE_ENOISE = -6    /* decryption noise budget exhausted (debug decrypt) */
+};
+
+typedef struct lrhe_ctx lrhe_ctx;
+typedef struct lrhe_sk lrhe_sk;       /* secret key: host memory only */
+typedef struct lrhe_pk lrhe_pk;       /* public key: device */
+typedef struct lrhe_gk lrhe_gk;       /* Galois (rotation) keys: device */
+typedef struct lrhe_model lrhe_model; /* encoded W^T and biases: device */
+typedef struct lrhe_server lrhe_server;
+
+typedef struct {
+  uint32_t n;               /* ring degree, power of two in [1024, 32768] */
+  uint32_t L;               /* number of data primes, 1..15 */
+  const uint32_t* q;        /* L data primes (host array, copied) */
+  uint32_t P;               /* special key-switching prime */
+  uint32_t t;               /* plaintext modulus, prime, < 2^30, = 1 mod 2n */
+  uint32_t allow_insecure;  /* nonzero: accept log2(Q P) above the 128-bit bound */
+} lrhe_params;
+
+/* Thread-local message describing the last error. */
+const char* lrhe_last_error(void);
+
+/* Create a context on HIP device `device`: validates the parameters
+ * (EPARAM), derives roots, twiddle and RNS tables and uploads them.
+ * device < 0 creates a host-only (client) context: key generation, key
+ * export, host decryption and host transforms work; device calls return
+ * LRHE_EDEVICE. */
+int lrhe_ctx_create(const lrhe_params* params, int device, lrhe_ctx** out);
+void lrhe_ctx_destroy(lrhe_ctx* ctx);
+/* n, L, number of rotation steps (log2 n) and uint32 words per ciphertext (2 L n). */
+int lrhe_ctx_info(const lrhe_ctx* ctx, uint32_t* n, uint32_t* L, uint32_t* ngal, uint64_t* ct_words);
+/* Galois element of rotation step i (0 <= i < ngal), in the order of the rotate-and-sum. */
+int lrhe_galois_element(const lrhe_ctx* ctx, uint32_t i, uint32_t* g);
+
+/* Key generation (client, protocol step "encrypted with the client's public
+ * key").  s ternary; pk = (-(a s + e), a); with_galois: the log2 n rotation
+ * keys ksk_{g,i} = (-(a s + e) + P [i = j] sigma_g(s), a) over q_0..q_{L-1}, P.
+ * Any of the output pointers may be NULL. */
+int lrhe_keygen(lrhe_ctx* ctx, uint64_t seed, int with_galois, lrhe_sk** sk, lrhe_pk** pk, lrhe_gk** gk);
+void lrhe_sk_destroy(lrhe_sk* sk);
+void lrhe_pk_destroy(lrhe_pk* pk);
+void lrhe_gk_destroy(lrhe_gk* gk);
+
+/* Workspace sizes (bytes) of the device calls below. */
+enum { LRHE_WS_ENCRYPT_ROWS = 1, LRHE_WS_ENCRYPT_COLS = 2, LRHE_WS_MATMUL_FAST = 3, LRHE_WS_MATMUL_STANDARD = 4 };
+int lrhe_workspace_bytes(const lrhe_ctx* ctx, int op, uint32_t rows, uint32_t f, uint32_t classes, uint64_t* bytes);
+
+/* Encode and encrypt X (device int64, rows x f, row-major; values taken mod t)
+ * in the fast layout of the protocol: row i, chunk k holds X[i][k n .. k n + n)
+ * in its slots (zero past f) and is ciphertext i K + k of ct_out, K = ceil(f/n).
+ * Randomness: stream seed `seed`, ciphertext id id0 + i K + k. */
+int lrhe_encrypt_rows(lrhe_ctx* ctx, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f,
+                      uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes, void* stream);
+/* Standard layout: ciphertext k (k < f) holds column X[.][k] in slots 0..rows-1
+ * (rows <= n); randomness id id0 + k. */
+int lrhe_encrypt_cols(lrhe_ctx* ctx, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f,
+                      uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Server-side model encoding: W (device int64, f x classes, row-major, the
+ * paper's f x |Y| weight matrix) transposed and packed n weights per
+ * plaintext, plus the all-slot bias plaintexts (bias: host int64[classes]).
+ * Also keeps the scalar weights the standard baseline needs. */
+int lrhe_model_create(lrhe_ctx* ctx, const int64_t* W, const int64_t* bias, uint32_t f, uint32_t classes,
+                      void* stream, lrhe_model** out);
+void lrhe_model_destroy(lrhe_model* m);
+
+/* Algorithm 1: Y^ = X^ x W- + B-.  xct: rows x K ciphertexts from
+ * lrhe_encrypt_rows with the model's f.  y_out: ceil(rows classes / n)
+ * ciphertexts; result (i, j) in ciphertext (i classes + j) / n, slot
+ * (i classes + j) mod n.  ws: lrhe_workspace_bytes(LRHE_WS_MATMUL_FAST). */
+int lrhe_matmul_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct,
+                     uint32_t rows, uint32_t* y_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Debug/parity variant of lrhe_matmul_fast: runs pairs [pair0, pair0 + npairs)
+ * (pair r = i classes + j) through the same kernels and writes each pair's
+ * ciphertext after `stage` to pairs_out (npairs ciphertexts):
+ * 0 = after the mask (before compression), 1 = after the chunk products and
+ * add_many, 2 + s = after s rotate-and-accumulate steps, 100 = after the bias. */
+int lrhe_matmul_fast_pairs(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct,
+                           uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* pairs_out,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Standard baseline: fct = f ciphertexts from lrhe_encrypt_cols;
+ * y_out[j] = sum_k fct[k] w_kj + B_j (classes ciphertexts); score (i, j) is
+ * slot i of y_out[j]. */
+int lrhe_matmul_standard(lrhe_ctx* ctx, const lrhe_model* model, const uint32_t* fct, uint32_t* y_out,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Client decryption: copies `count` ciphertexts from the device, decrypts them
+ * on the host with the secret key and decodes the slots, centred into
+ * (-t/2, t/2] (slots: host int64[count][n]).  budgets (optional, host
+ * double[count]): remaining noise budget log2(Q/2) - log2 max|[t x]_Q| in bits. */
+int lrhe_decrypt_slots(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, int64_t* slots,
+                       double* budgets, void* stream);
+
+/* Same as lrhe_decrypt_slots for ciphertexts already in host memory (same layout). */
+int lrhe_decrypt_slots_host(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, int64_t* slots,
+                            double* budgets);
+/* Host (client-side) transform of one polynomial in place, modulus index
+ * mod_index (0..L-1 data primes, L = P, L+1 = t): forward maps canonical
+ * coefficients to evaluations at psi^(2 brv(k)+1) stored at index k (the
+ * device's evaluation layout); inverse maps back.  Runs the same pass
+ * arithmetic as the kernels. */
+int lrhe_host_transform(lrhe_ctx* ctx, uint32_t mod_index, uint32_t* a, int inverse);
+
+/* Canonical coefficient form of `polys` device polynomials of L limbs each
+ * (ciphertexts are 2 such polys): inverse transform per limb, output in
+ * [0, q_i) to out (device, same shape).  Used for parity checks. */
+int lrhe_to_coeff(lrhe_ctx* ctx, const uint32_t* in, uint64_t polys, uint32_t* out, void* stream);
+/* Batched negacyclic transform in place on `polys` device polynomials of L
+ * limbs each (limb i modulo q_i): forward maps canonical coefficients to the
+ * evaluation form the kernels use, inverse maps back (canonical output). */
+int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* stream);
+
+/* Opt-in kernel timing: while enabled, every kernel launch of the library is
+ * bracketed by HIP events on its own stream.  lrhe_prof_get returns the number
+ * of launches and their summed duration (ms) for a kernel name (for example
+ * "k_ks_mac", "k_ntt_fwd") since the last reset; it waits for pending events. */
+void lrhe_prof_enable(int on);
+void lrhe_prof_reset(void);
+int lrhe_prof_get(const char* kernel, uint64_t* launches, double* total_ms);
+
+/* Keys in canonical coefficient form on the host: pk as uint32 [2][L][n];
+ * gk as uint32 [ngal][L digits][2][L+1 moduli][n] (last modulus = P). */
+int lrhe_pk_export(lrhe_ctx* ctx, const lrhe_pk* pk, uint32_t* host_out);
+int lrhe_gk_export(lrhe_ctx* ctx, const lrhe_gk* gk, uint32_t* host_out);
+/* Secret key coefficients (ternary, host int8[n]); client-side only. */
+int lrhe_sk_export(lrhe_ctx* ctx, const lrhe_sk* sk, int8_t* host_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRHE_H */

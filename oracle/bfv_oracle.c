@@ -618,8 +618,8 @@ void ora_onehot_plain(const ora_ctx* c, int l, u64* m) {
 /* Algorithm 1 for one (input i, output j) pair up to the masked ciphertext.
  * xct: the K ciphertexts of row i; wpt: the K plaintexts (values mod t) of
  * class j; bias_t: b_j mod t; slot: l = (i |W| + j) mod n.
- * stage (debug): 0 = full; 1 = stop after add_many; 2 + s = stop after s rotation steps;
- * 100 = stop after the bias. */
+ * stage (debug): 0 = full; 1 = stop after add_many; 2 + s = stop after s rotation steps
+ * (s <= log2 n); 100 = stop after the bias. */
 void ora_pair(const ora_ctx* c, const u64* gk, const u64* gk_ev, const u64* xct, const u64* wpt, int K,
               u64 bias_t, int slot, int stage, u64* out) {
   const int n = c->n, L = c->L;
@@ -635,6 +635,7 @@ void ora_pair(const ora_ctx* c, const u64* gk, const u64* gk_ev, const u64* xct,
     if (stage >= 2 && stage < 100 && gi == stage - 2) { free(tmp); return; }
     ora_rotate_add(c, gk, gk_ev, gi, out);
   }
+  if (stage == 2 + c->ngal) { free(tmp); return; }   /* after every rotation step */
   ora_add_const(c, bias_t, out);          /* all-slot bias b_j */
   if (stage == 100) { free(tmp); return; }
   u64* mu = (u64*)malloc(sizeof(u64) * n); /* masking */

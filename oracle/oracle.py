@@ -181,9 +181,9 @@ class Oracle:
         lib().ora_encrypt(self.ctx, P(keys.pk), P(u64(m)), seed, ct_id, P(ct))
         return ct
 
-    def encrypt_rows(self, keys: Keys, X: np.ndarray, seed: int) -> np.ndarray:
+    def encrypt_rows(self, keys: Keys, X: np.ndarray, seed: int, row0: int = 0) -> np.ndarray:
         """Fast layout: row i, chunk k holds X[i, k n : (k+1) n] in its slots
-        (zero past f); ciphertext id = i K + k.  Returns [rows][K][2][L][n]."""
+        (zero past f); ciphertext id = (row0 + i) K + k.  Returns [rows][K][2][L][n]."""
         rows, f = X.shape
         K = -(-f // self.n)
         out = np.zeros((rows, K, 2, self.L, self.n), dtype=np.uint64)
@@ -192,7 +192,7 @@ class Oracle:
                 z = np.zeros(self.n, dtype=np.int64)
                 chunk = X[i, k * self.n:(k + 1) * self.n]
                 z[:len(chunk)] = chunk
-                out[i, k] = self.encrypt_plain(keys, self.encode(z), seed, i * K + k)
+                out[i, k] = self.encrypt_plain(keys, self.encode(z), seed, (row0 + i) * K + k)
         return out
 
     def encrypt_cols(self, keys: Keys, X: np.ndarray, seed: int, features=None) -> np.ndarray:
@@ -312,8 +312,14 @@ def P_(a):
 def plain_scores(X: np.ndarray, W: np.ndarray, bias, t: int) -> np.ndarray:
     """The result the method must reach: [X W + b]_t centred into (-t/2, t/2]
     (section "Private inference protocol"; integer arithmetic, exact)."""
-    S = (X.astype(object) @ W.astype(object)) + np.asarray(bias, dtype=object)[None, :]
-    S = np.vectorize(lambda v: int(v) % t)(S).astype(np.int64)
+    X64, W64, b64 = (np.asarray(a, dtype=np.int64) for a in (X, W, bias))
+    bound = int(np.abs(X64).max(initial=0)) * int(np.abs(W64).max(initial=0)) * X64.shape[1] + \
+        int(np.abs(b64).max(initial=0))
+    if bound < 2**62:   # every partial sum fits: int64 arithmetic is exact
+        S = (X64 @ W64 + b64[None, :]) % t
+    else:
+        S = (X64.astype(object) @ W64.astype(object)) + b64.astype(object)[None, :]
+        S = np.vectorize(lambda v: int(v) % t)(S).astype(np.int64)
     return np.where(S > (t - 1) // 2, S - t, S)
 
 

@@ -1,0 +1,252 @@
+"""Python front end of liblrhe: the calls of the paper's private inference
+protocol (section "Private inference protocol") on one MI355X.
+
+    ctx = Context(n, q, P, t)             # parameters {n, T} of the protocol
+    keys = ctx.keygen(seed)               # client: sk (host), pk, Galois keys (HBM)
+    xct = ctx.encrypt_rows(keys, X, seed) # client: encode + encrypt |X| x f
+    model = ctx.model(W, b)               # server: encode W^T and the biases
+    y = ctx.matmul_fast(keys, model, xct, rows)      # server: Algorithm 1
+    S, budget = ctx.scores_fast(keys, y, rows, classes)  # client: decrypt, decode
+    cls = S.argmax(1)                     # predicted class
+
+Ciphertext tensors are torch.int32 [count, 2, L, n] on the GPU holding uint32
+residues (evaluation form).  All arithmetic happens in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import native as N
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Keys:
+    ctx: "Context"
+    sk: ctypes.c_void_p
+    pk: ctypes.c_void_p
+    gk: ctypes.c_void_p
+
+    def close(self):
+        lib = N.lib()
+        if self.sk:
+            lib.lrhe_sk_destroy(self.sk)
+        if self.pk:
+            lib.lrhe_pk_destroy(self.pk)
+        if self.gk:
+            lib.lrhe_gk_destroy(self.gk)
+        self.sk = self.pk = self.gk = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Model:
+    ctx: "Context"
+    handle: ctypes.c_void_p
+    f: int
+    classes: int
+
+    def close(self):
+        if self.handle:
+            N.lib().lrhe_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """BFV context on one device (device < 0: host-only client context)."""
+
+    def __init__(self, n: int, q, P: int, t: int, device: int = 0, allow_insecure: bool = False):
+        lib = N.lib()
+        self._q = (ctypes.c_uint32 * len(q))(*q)
+        prm = N.LrheParams(n, len(q), self._q, P, t, 1 if allow_insecure else 0)
+        h = ctypes.c_void_p()
+        N.check(lib.lrhe_ctx_create(ctypes.byref(prm), device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        nn, LL, ng, cw = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        N.check(lib.lrhe_ctx_info(h, ctypes.byref(nn), ctypes.byref(LL), ctypes.byref(ng), ctypes.byref(cw)))
+        self.n, self.L, self.ngal, self.ct_words = nn.value, LL.value, ng.value, cw.value
+        self.q, self.P, self.t = list(q), P, t
+        g = ctypes.c_uint32()
+        self.gal = []
+        for i in range(self.ngal):
+            N.check(lib.lrhe_galois_element(h, i, ctypes.byref(g)))
+            self.gal.append(g.value)
+
+    @classmethod
+    def from_params(cls, p, device: int = 0):
+        return cls(p.n, list(p.q), p.P, p.t, device=device, allow_insecure=p.insecure)
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().lrhe_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- buffers
+    def _dev(self):
+        return _torch().device("cuda", self.device)
+
+    def empty_ct(self, count: int):
+        torch = _torch()
+        return torch.empty((count, 2, self.L, self.n), dtype=torch.int32, device=self._dev())
+
+    def workspace(self, op: int, rows: int = 0, f: int = 0, classes: int = 0):
+        b = ctypes.c_uint64()
+        N.check(N.lib().lrhe_workspace_bytes(self.h, op, rows, f, classes, ctypes.byref(b)))
+        torch = _torch()
+        return torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=self._dev())
+
+    def K(self, f: int) -> int:
+        return -(-f // self.n)
+
+    # ---------------------------------------------------------------- keys
+    def keygen(self, seed: int, galois: bool = True) -> Keys:
+        sk, pk, gk = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        N.check(N.lib().lrhe_keygen(self.h, seed, 1 if galois else 0, ctypes.byref(sk), ctypes.byref(pk),
+                                    ctypes.byref(gk) if galois else None))
+        return Keys(self, sk, pk, gk if galois else None)
+
+    def export_pk(self, keys: Keys) -> np.ndarray:
+        out = np.zeros((2, self.L, self.n), dtype=np.uint32)
+        N.check(N.lib().lrhe_pk_export(self.h, keys.pk, N.ptr(out)))
+        return out
+
+    def export_gk(self, keys: Keys) -> np.ndarray:
+        out = np.zeros((self.ngal, self.L, 2, self.L + 1, self.n), dtype=np.uint32)
+        N.check(N.lib().lrhe_gk_export(self.h, keys.gk, N.ptr(out)))
+        return out
+
+    def export_sk(self, keys: Keys) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int8)
+        N.check(N.lib().lrhe_sk_export(self.h, keys.sk, N.ptr(out)))
+        return out
+
+    # ---------------------------------------------------------------- client
+    def _as_dev_i64(self, X):
+        torch = _torch()
+        if isinstance(X, np.ndarray):
+            X = torch.from_numpy(np.ascontiguousarray(X, dtype=np.int64))
+        return X.to(device=self._dev(), dtype=torch.int64).contiguous()
+
+    def encrypt_rows(self, keys: Keys, X, seed: int, id0: int = 0, out=None, ws=None):
+        """Fast layout: [rows * K] ciphertexts (row i, chunk k at i K + k)."""
+        Xd = self._as_dev_i64(X)
+        rows, f = Xd.shape
+        K = self.K(f)
+        out = self.empty_ct(rows * K) if out is None else out
+        ws = self.workspace(N.WS_ENCRYPT_ROWS, rows, f) if ws is None else ws
+        N.check(N.lib().lrhe_encrypt_rows(self.h, keys.pk, N.ptr(Xd), rows, f, seed, id0, N.ptr(out), N.ptr(ws),
+                                          ws.numel(), _stream()))
+        return out
+
+    def encrypt_cols(self, keys: Keys, X, seed: int, id0: int = 0, out=None, ws=None):
+        """Standard layout: f ciphertexts, individuals in slots."""
+        Xd = self._as_dev_i64(X)
+        rows, f = Xd.shape
+        out = self.empty_ct(f) if out is None else out
+        ws = self.workspace(N.WS_ENCRYPT_COLS, rows, f) if ws is None else ws
+        N.check(N.lib().lrhe_encrypt_cols(self.h, keys.pk, N.ptr(Xd), rows, f, seed, id0, N.ptr(out), N.ptr(ws),
+                                          ws.numel(), _stream()))
+        return out
+
+    def decrypt_slots(self, keys: Keys, ct):
+        cnt = ct.shape[0]
+        slots = np.zeros((cnt, self.n), dtype=np.int64)
+        bud = np.zeros(cnt, dtype=np.float64)
+        N.check(N.lib().lrhe_decrypt_slots(self.h, keys.sk, N.ptr(ct.contiguous()), cnt, N.ptr(slots), N.ptr(bud),
+                                           _stream()))
+        return slots, bud
+
+    def decrypt_slots_host(self, keys: Keys, ct_host: np.ndarray):
+        ct_host = np.ascontiguousarray(ct_host, dtype=np.uint32)
+        cnt = ct_host.shape[0]
+        slots = np.zeros((cnt, self.n), dtype=np.int64)
+        bud = np.zeros(cnt, dtype=np.float64)
+        N.check(N.lib().lrhe_decrypt_slots_host(self.h, keys.sk, N.ptr(ct_host), cnt, N.ptr(slots), N.ptr(bud)))
+        return slots, bud
+
+    def scores_fast(self, keys: Keys, y, rows: int, classes: int):
+        slots, bud = self.decrypt_slots(keys, y)
+        r = np.arange(rows * classes)
+        S = slots[r // self.n, r % self.n].reshape(rows, classes)
+        return S, float(bud.min())
+
+    def scores_standard(self, keys: Keys, y, rows: int):
+        slots, bud = self.decrypt_slots(keys, y)
+        return slots[:, :rows].T.copy(), float(bud.min())
+
+    def host_transform(self, a: np.ndarray, mod_index: int, inverse: bool = False) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=np.uint32).copy()
+        N.check(N.lib().lrhe_host_transform(self.h, mod_index, N.ptr(a), 1 if inverse else 0))
+        return a
+
+    # ---------------------------------------------------------------- server
+    def model(self, W, bias) -> Model:
+        Wd = self._as_dev_i64(W)
+        f, classes = Wd.shape
+        b = np.ascontiguousarray(bias, dtype=np.int64)
+        h = ctypes.c_void_p()
+        N.check(N.lib().lrhe_model_create(self.h, N.ptr(Wd), N.ptr(b), f, classes, _stream(), ctypes.byref(h)))
+        return Model(self, h, f, classes)
+
+    def matmul_fast(self, keys: Keys, model: Model, xct, rows: int, out=None, ws=None):
+        nout = -(-rows * model.classes // self.n)
+        out = self.empty_ct(nout) if out is None else out
+        ws = self.workspace(N.WS_MATMUL_FAST, rows, model.f, model.classes) if ws is None else ws
+        N.check(N.lib().lrhe_matmul_fast(self.h, keys.gk, model.handle, N.ptr(xct), rows, N.ptr(out), N.ptr(ws),
+                                         ws.numel(), _stream()))
+        return out
+
+    def matmul_fast_pairs(self, keys: Keys, model: Model, xct, rows: int, pair0: int, npairs: int, stage: int,
+                          out=None, ws=None):
+        out = self.empty_ct(npairs) if out is None else out
+        ws = self.workspace(N.WS_MATMUL_FAST, npairs, model.f, 1) if ws is None else ws
+        N.check(N.lib().lrhe_matmul_fast_pairs(self.h, keys.gk, model.handle, N.ptr(xct), rows, pair0, npairs, stage,
+                                               N.ptr(out), N.ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def matmul_standard(self, model: Model, fct, out=None):
+        out = self.empty_ct(model.classes) if out is None else out
+        N.check(N.lib().lrhe_matmul_standard(self.h, model.handle, N.ptr(fct), N.ptr(out), None, 0, _stream()))
+        return out
+
+    def to_coeff(self, ct):
+        """Canonical coefficient form (device tensor, same shape), for parity checks."""
+        out = _torch().empty_like(ct)
+        polys = ct.numel() // (self.L * self.n)
+        N.check(N.lib().lrhe_to_coeff(self.h, N.ptr(ct.contiguous()), polys, N.ptr(out), _stream()))
+        return out
+
+
+def to_numpy_u32(t) -> np.ndarray:
+    """Device int32 tensor of residues -> host uint32 array."""
+    return t.cpu().numpy().view(np.uint32)

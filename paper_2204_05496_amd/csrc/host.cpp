@@ -1,0 +1,817 @@
+// host.cpp -- host runtime of the encrypted logistic-regression library:
+// parameter validation, root/twiddle/RNS tables, key generation (client),
+// exact decryption (client) and the C ABI entry points of include/lrhe.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lrhe_internal.h"
+
+using namespace lrhe;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+#define NEED_DEVICE(c) \
+  do { if ((c)->device < 0) return fail(LRHE_EDEVICE, "host-only context (device < 0) has no GPU"); } while (0)
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(LRHE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* lrhe_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ number theory (host)
+static uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+static uint64_t powmod64(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  while (e) {
+    if (e & 1) r = mulmod64(r, b, m);
+    b = mulmod64(b, b, m);
+    e >>= 1;
+  }
+  return r;
+}
+static bool is_prime(uint64_t p) {
+  if (p < 2) return false;
+  for (uint64_t d : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull}) {
+    if (p % d == 0) return p == d;
+  }
+  // deterministic Miller-Rabin for 64-bit inputs
+  uint64_t d = p - 1;
+  int s = 0;
+  while ((d & 1) == 0) { d >>= 1; ++s; }
+  for (uint64_t a : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull}) {
+    uint64_t x = powmod64(a, d, p);
+    if (x == 1 || x == p - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod64(x, x, p);
+      if (x == p - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+static uint64_t min_generator(uint64_t p) {
+  std::vector<uint64_t> fac;
+  uint64_t m = p - 1;
+  for (uint64_t d = 2; d * d <= m; ++d)
+    if (m % d == 0) {
+      fac.push_back(d);
+      while (m % d == 0) m /= d;
+    }
+  if (m > 1) fac.push_back(m);
+  for (uint64_t g = 2; g < p; ++g) {
+    bool ok = true;
+    for (uint64_t f : fac)
+      if (powmod64(g, (p - 1) / f, p) == 1) { ok = false; break; }
+    if (ok) return g;
+  }
+  return 0;
+}
+static uint32_t inv_mod(uint64_t a, uint64_t p) { return (uint32_t)powmod64(a % p, p - 2, p); }
+
+static Mod make_mod(uint32_t q, uint32_t n) {
+  Mod m;
+  m.q = q;
+  uint32_t inv = 1;   // q^-1 mod 2^32 by Newton iteration
+  for (int i = 0; i < 5; ++i) inv *= 2 - q * inv;
+  m.qinv = (uint32_t)(0u - inv);
+  const uint64_t R = (1ull << 32) % q;
+  m.r2 = (uint32_t)mulmod64(R, R, q);
+  m.ninv_m = (uint32_t)mulmod64(inv_mod(n, q), R, q);
+  return m;
+}
+
+// maximum log2(Q P) for 128-bit security with a ternary secret (HE standard tables)
+static double security_bound_bits(uint32_t n) {
+  switch (n) {
+    case 1024: return 27; case 2048: return 54; case 4096: return 109;
+    case 8192: return 218; case 16384: return 438; case 32768: return 881;
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ host transforms
+// The host runs the very same pass functions as the kernels, one emulated
+// thread at a time, with the exchange done through a plain array.
+template <int LOGN>
+static void host_ntt_t(uint32_t* a, const uint32_t* tw, const Mod& m, bool inverse) {
+  using G = Geom<LOGN, 5>;
+  std::vector<uint32_t> X((size_t)G::N), tmp((size_t)G::N);
+  auto load = [&](int p) {
+    for (int t = 0; t < G::T; ++t)
+      for (int e = 0; e < G::E; ++e) X[(size_t)t * G::E + e] = tmp[G::idx(p, t, e)];
+  };
+  auto store = [&](int p) {
+    for (int t = 0; t < G::T; ++t)
+      for (int e = 0; e < G::E; ++e) tmp[G::idx(p, t, e)] = X[(size_t)t * G::E + e];
+  };
+  std::copy(a, a + G::N, tmp.begin());
+  if (!inverse) {
+    for (int p = 0; p < G::NPASS; ++p) {
+      load(p);
+      for (int t = 0; t < G::T; ++t) fwd_pass<G>(p, t, &X[(size_t)t * G::E], tw, m.q, m.qinv);
+      store(p);
+    }
+    for (int i = 0; i < G::N; ++i) a[i] = red2(tmp[i], m.q);
+  } else {
+    for (int p = G::NPASS - 1; p >= 0; --p) {
+      load(p);
+      for (int t = 0; t < G::T; ++t) inv_pass<G>(p, t, &X[(size_t)t * G::E], tw, m.q, m.qinv);
+      store(p);
+    }
+    for (int i = 0; i < G::N; ++i) a[i] = red1(mulm(tmp[i], m.ninv_m, m.q, m.qinv), m.q);
+  }
+}
+// forward: natural coefficients (< 4q) -> evaluations, bit-reversed order; inverse: back
+static void host_ntt(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
+  const uint32_t* tb = (inverse ? c->h_itw.data() : c->h_tw.data()) + (size_t)mi * c->n;
+  const Mod& m = c->mods[mi];
+  switch (c->logn) {
+    case 10: host_ntt_t<10>(a, tb, m, inverse); break;
+    case 11: host_ntt_t<11>(a, tb, m, inverse); break;
+    case 12: host_ntt_t<12>(a, tb, m, inverse); break;
+    case 13: host_ntt_t<13>(a, tb, m, inverse); break;
+    case 14: host_ntt_t<14>(a, tb, m, inverse); break;
+    case 15: host_ntt_t<15>(a, tb, m, inverse); break;
+  }
+}
+
+// ------------------------------------------------------------------ context
+extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out) {
+  if (!p || !out) return fail(LRHE_EINVAL, "null argument");
+  *out = nullptr;
+  const uint32_t n = p->n;
+  if (n < (1u << LRHE_MINLOGN) || n > (1u << LRHE_MAXLOGN) || (n & (n - 1)))
+    return fail(LRHE_EPARAM, "n = %u: must be a power of two in [%u, %u]", n, 1u << LRHE_MINLOGN, 1u << LRHE_MAXLOGN);
+  if (p->L < 1 || p->L > LRHE_MAXL) return fail(LRHE_EPARAM, "L = %u: must be in [1, %d]", p->L, LRHE_MAXL);
+  if (!p->q) return fail(LRHE_EINVAL, "q is null");
+  std::vector<uint32_t> qs(p->q, p->q + p->L);
+  qs.push_back(p->P);
+  double logqp = 0;
+  for (size_t i = 0; i < qs.size(); ++i) {
+    const uint32_t q = qs[i];
+    if (q <= (1u << 28) || q >= (1u << 30))
+      return fail(LRHE_EPARAM, "modulus %u outside (2^28, 2^30)", q);
+    if (!is_prime(q)) return fail(LRHE_EPARAM, "modulus %u is not prime", q);
+    if ((q - 1) % (2 * n)) return fail(LRHE_EPARAM, "modulus %u is not 1 mod 2n", q);
+    for (size_t k = 0; k < i; ++k)
+      if (qs[k] == q) return fail(LRHE_EPARAM, "modulus %u repeated", q);
+    logqp += std::log2((double)q);
+  }
+  if (p->t < 3 || p->t >= (1u << 30) || !is_prime(p->t) || (p->t - 1) % (2 * n))
+    return fail(LRHE_EPARAM, "t = %u: must be a prime < 2^30 that is 1 mod 2n", p->t);
+  for (uint32_t q : qs)
+    if (q == p->t) return fail(LRHE_EPARAM, "t equals a ciphertext modulus");
+  if (!p->allow_insecure && logqp > security_bound_bits(n))
+    return fail(LRHE_EPARAM, "log2(Q P) = %.1f exceeds the 128-bit bound %.0f for n = %u (set allow_insecure)",
+                logqp, security_bound_bits(n), n);
+
+  auto* c = new lrhe_ctx();
+  c->device = device;
+  c->n = n;
+  while ((1u << c->logn) < n) c->logn++;
+  c->L = p->L;
+  c->q = qs;
+  c->P = p->P;
+  c->t = p->t;
+  const uint32_t L = c->L;
+  // Galois elements: rotations by n/4, ..., 1 within the rows, then the row swap
+  for (uint32_t s = n / 4; s >= 1; s /= 2) c->gal.push_back((uint32_t)powmod64(3, s, 2 * n));
+  c->gal.push_back(2 * n - 1);
+  c->ngal = (uint32_t)c->gal.size();
+  // moduli and twiddle tables (data primes, P, t)
+  std::vector<uint32_t> all = qs;
+  all.push_back(p->t);
+  c->h_tw.assign((size_t)(L + 2) * n, 0);
+  c->h_itw.assign((size_t)(L + 2) * n, 0);
+  for (uint32_t mi = 0; mi < L + 2; ++mi) {
+    const uint32_t q = all[mi];
+    c->mods.push_back(make_mod(q, n));
+    const uint64_t g = min_generator(q);
+    const uint64_t psi = powmod64(g, (q - 1) / (2 * n), q);
+    const uint64_t ipsi = inv_mod(psi, q);
+    const uint64_t R = (1ull << 32) % q;
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t e = brv(k, (int)c->logn);
+      c->h_tw[(size_t)mi * n + k] = (uint32_t)mulmod64(powmod64(psi, e, q), R, q);
+      c->h_itw[(size_t)mi * n + k] = (uint32_t)mulmod64(powmod64(ipsi, e, q), R, q);
+    }
+  }
+  // slot layout mod t: slot j <-> psi_t^(e_j); in the bit-reversed transform the
+  // evaluation at psi_t^(2m+1) sits at index brv(m)
+  const uint32_t t = p->t;
+  const uint64_t psit = powmod64(min_generator(t), (t - 1) / (2 * n), t);
+  c->slot_exp.resize(n);
+  c->slot_pos.resize(n);
+  c->pos_slot.resize(n);
+  uint64_t e = 1;
+  for (uint32_t j = 0; j < n / 2; ++j) {
+    c->slot_exp[j] = (uint32_t)e;
+    c->slot_exp[n / 2 + j] = (uint32_t)(2 * n - e);
+    e = e * 3 % (2 * n);
+  }
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint32_t k = brv((c->slot_exp[j] - 1) / 2, (int)c->logn);
+    c->slot_pos[j] = k;
+    c->pos_slot[k] = j;
+  }
+  // one-hot mask coefficients: mu_{l,k} = n^-1 psi_t^-(e_l k); table over x = e_l k mod 2n
+  c->mask_tab.resize(2 * n);
+  const uint64_t ninv_t = inv_mod(n, t), ipsit = inv_mod(psit, t);
+  for (uint32_t x = 0; x < 2 * n; ++x) c->mask_tab[x] = (uint32_t)mulmod64(ninv_t, powmod64(ipsit, x, t), t);
+  // BFV constants
+  DevCtx& d = c->dc;
+  d.n = n;
+  d.logn = c->logn;
+  d.L = L;
+  for (uint32_t mi = 0; mi < L + 2; ++mi) d.mod[mi] = c->mods[mi];
+  d.t = t;
+  uint64_t qmt = 1;
+  for (uint32_t i = 0; i < L; ++i) qmt = qmt * (qs[i] % t) % t;
+  d.qmodt = (uint32_t)qmt;
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint64_t q = qs[i], R = (1ull << 32) % q;
+    // floor(Q/t) mod q_i = -(Q mod t) t^-1 mod q_i (Q = 0 mod q_i)
+    const uint64_t qd = mulmod64((q - qmt % q) % q, inv_mod(t, q), q);
+    d.qdivt_m[i] = (uint32_t)mulmod64(qd, R, q);
+    d.pinv_m[i] = (uint32_t)mulmod64(inv_mod(p->P, q), R, q);
+    d.hmod[i] = (uint32_t)(((uint64_t)(p->P - 1) / 2) % q);
+  }
+  // decryption constants: y_j = (Q/q_j)^-1 mod q_j, t y_j = I_j q_j + R_j
+  {
+    std::vector<uint32_t> Q = {1};
+    auto mul_small = [](std::vector<uint32_t>& a, uint32_t m) {
+      uint64_t carry = 0;
+      for (auto& w : a) {
+        uint64_t v = (uint64_t)w * m + carry;
+        w = (uint32_t)v;
+        carry = v >> 32;
+      }
+      if (carry) a.push_back((uint32_t)carry);
+    };
+    for (uint32_t i = 0; i < L; ++i) mul_small(Q, qs[i]);
+    c->Qbig = Q;
+    c->log2Q = 0;
+    for (uint32_t i = 0; i < L; ++i) c->log2Q += std::log2((double)qs[i]);
+    for (uint32_t j = 0; j < L; ++j) {
+      std::vector<uint32_t> Qh = {1};
+      uint64_t qh_mod = 1;
+      for (uint32_t i = 0; i < L; ++i)
+        if (i != j) {
+          mul_small(Qh, qs[i]);
+          qh_mod = qh_mod * qs[i] % qs[j];
+        }
+      c->Qhat.push_back(Qh);
+      const uint64_t y = inv_mod(qh_mod, qs[j]);
+      const uint64_t ty = (uint64_t)t * y;
+      c->dec_I.push_back((uint32_t)((ty / qs[j]) % t));
+      c->dec_R.push_back((uint32_t)(ty % qs[j]));
+      c->dec_Rf.push_back((double)(ty % qs[j]) / (double)qs[j]);
+    }
+  }
+  *out = c;
+  if (device < 0) return LRHE_OK;   // host-only context: client-side host code, no device tables
+  *out = nullptr;
+  // upload
+  hipError_t err = hipSetDevice(device);
+  if (err != hipSuccess) { delete c; return fail(LRHE_EDEVICE, "hipSetDevice(%d): %s", device, hipGetErrorString(err)); }
+  auto up = [&](uint32_t** dst, const std::vector<uint32_t>& src) -> hipError_t {
+    hipError_t e2 = hipMalloc((void**)dst, src.size() * 4);
+    if (e2 != hipSuccess) return e2;
+    return hipMemcpy(*dst, src.data(), src.size() * 4, hipMemcpyHostToDevice);
+  };
+  if ((err = up(&c->d_tw, c->h_tw)) != hipSuccess || (err = up(&c->d_itw, c->h_itw)) != hipSuccess ||
+      (err = up(&c->d_pos_slot, c->pos_slot)) != hipSuccess || (err = up(&c->d_slot_exp, c->slot_exp)) != hipSuccess ||
+      (err = up(&c->d_mask_tab, c->mask_tab)) != hipSuccess) {
+    lrhe_ctx_destroy(c);
+    return fail(LRHE_EDEVICE, "context upload: %s", hipGetErrorString(err));
+  }
+  d.tw = c->d_tw;
+  d.itw = c->d_itw;
+  d.pos_slot = c->d_pos_slot;
+  d.slot_exp = c->d_slot_exp;
+  d.mask_tab = c->d_mask_tab;
+  *out = c;
+  return LRHE_OK;
+}
+
+extern "C" void lrhe_ctx_destroy(lrhe_ctx* c) {
+  if (!c) return;
+  if (c->device < 0) {
+    delete c;
+    return;
+  }
+  (void)hipSetDevice(c->device);
+  (void)hipFree(c->d_tw);
+  (void)hipFree(c->d_itw);
+  (void)hipFree(c->d_pos_slot);
+  (void)hipFree(c->d_slot_exp);
+  (void)hipFree(c->d_mask_tab);
+  delete c;
+}
+
+extern "C" int lrhe_ctx_info(const lrhe_ctx* c, uint32_t* n, uint32_t* L, uint32_t* ngal, uint64_t* ct_words) {
+  if (!c) return fail(LRHE_EINVAL, "null context");
+  if (n) *n = c->n;
+  if (L) *L = c->L;
+  if (ngal) *ngal = c->ngal;
+  if (ct_words) *ct_words = (uint64_t)2 * c->L * c->n;
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_galois_element(const lrhe_ctx* c, uint32_t i, uint32_t* g) {
+  if (!c || !g || i >= c->ngal) return fail(LRHE_EINVAL, "bad Galois index");
+  *g = c->gal[i];
+  return LRHE_OK;
+}
+
+// ------------------------------------------------------------------ keys (client)
+struct Stream {
+  uint64_t seed;
+  uint32_t kind;
+  uint64_t id;
+  uint32_t cur = 0xffffffffu, blk[16];
+  uint32_t word(uint64_t w) {
+    const uint32_t b = (uint32_t)(w >> 4);
+    if (b != cur) {
+      chacha20(seed, kind, id, b, blk);
+      cur = b;
+    }
+    return blk[w & 15];
+  }
+};
+static void sample_ternary(uint64_t seed, uint32_t kind, uint64_t id, uint32_t n, std::vector<int32_t>& out) {
+  Stream S{seed, kind, id};
+  out.resize(n);
+  for (uint32_t k = 0; k < n; ++k) out[k] = ternary_of(S.word(k));
+}
+static void sample_cbd(uint64_t seed, uint32_t kind, uint64_t id, uint32_t n, std::vector<int32_t>& out) {
+  Stream S{seed, kind, id};
+  out.resize(n);
+  for (uint32_t k = 0; k < n; ++k) out[k] = cbd21_of(S.word(2ull * k), S.word(2ull * k + 1));
+}
+static void sample_uniform(uint64_t seed, uint32_t kind, uint64_t id, uint32_t m, uint32_t n, uint32_t* out) {
+  Stream S{seed, kind, id};
+  for (uint32_t k = 0; k < n; ++k) out[k] = uniform_of(S.word(2ull * k), S.word(2ull * k + 1), m);
+}
+static uint32_t smod(int64_t v, uint32_t q) {
+  int64_t r = v % (int64_t)q;
+  return (uint32_t)(r < 0 ? r + q : r);
+}
+
+// sigma_g on integer coefficients: a(X) -> a(X^g) mod X^n + 1
+static void automorph_int(const std::vector<int32_t>& a, uint32_t g, uint32_t n, std::vector<int32_t>& out) {
+  out.assign(n, 0);
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint64_t idx = (uint64_t)g * k % (2 * n);
+    if (idx < n) out[idx] = a[k];
+    else out[idx - n] = -a[k];
+  }
+}
+
+extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk** sk_out, lrhe_pk** pk_out,
+                           lrhe_gk** gk_out) {
+  if (!c) return fail(LRHE_EINVAL, "null context");
+  const uint32_t n = c->n, L = c->L;
+  std::vector<int32_t> s, e;
+  sample_ternary(seed, KIND_SECRET, 0, n, s);
+  // s in evaluation form for every modulus (data primes and P)
+  std::vector<uint32_t> S((size_t)(L + 1) * n);
+  for (uint32_t r = 0; r <= L; ++r) {
+    uint32_t* Sr = &S[(size_t)r * n];
+    for (uint32_t k = 0; k < n; ++k) Sr[k] = smod(s[k], c->q[r]);
+    host_ntt(c, (int)r, Sr, false);
+  }
+  auto* sk = new lrhe_sk();
+  sk->n = n;
+  sk->L = L;
+  sk->s.assign(s.begin(), s.end());
+  sk->S.assign(S.begin(), S.begin() + (size_t)L * n);
+  // public key: pk = (-(a s + e), a) mod Q, evaluation form
+  auto* pk = new lrhe_pk();
+  pk->h.assign((size_t)2 * L * n, 0);
+  sample_cbd(seed, KIND_PK_E, 0, n, e);
+  std::vector<uint32_t> A(n), Ev(n);
+  for (uint32_t j = 0; j < L; ++j) {
+    const uint32_t q = c->q[j];
+    sample_uniform(seed, KIND_PK_A, j, q, n, A.data());
+    host_ntt(c, (int)j, A.data(), false);
+    for (uint32_t k = 0; k < n; ++k) Ev[k] = smod(e[k], q);
+    host_ntt(c, (int)j, Ev.data(), false);
+    const uint32_t* Sj = &S[(size_t)j * n];
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint64_t as = (uint64_t)A[k] * Sj[k] % q;
+      pk->h[(size_t)j * n + k] = (uint32_t)((2ull * q - as - Ev[k]) % q);
+      pk->h[(size_t)(L + j) * n + k] = A[k];
+    }
+  }
+  const bool dev = c->device >= 0;
+  hipError_t err = dev ? hipSetDevice(c->device) : hipSuccess;
+  if (err == hipSuccess && dev) err = hipMalloc((void**)&pk->d, pk->h.size() * 4);
+  if (err != hipSuccess) {
+    delete sk;
+    delete pk;
+    return fail(LRHE_EDEVICE, "pk allocation: %s", hipGetErrorString(err));
+  }
+  {
+    std::vector<uint32_t> mont(pk->h.size());
+    for (size_t x = 0; x < mont.size(); ++x) mont[x] = to_mont(pk->h[x], c->mods[(x / n) % L]);
+    if (dev) err = hipMemcpy(pk->d, mont.data(), mont.size() * 4, hipMemcpyHostToDevice);
+  }
+  lrhe_gk* gk = nullptr;
+  if (err == hipSuccess && with_galois) {
+    gk = new lrhe_gk();
+    gk->words = (size_t)c->ngal * (L + 1) * L * 2 * n;
+    gk->h.assign(gk->words, 0);
+    // ksk_{g,i} mod r = (-(a s + e) + [P]_r [i = r] sigma_g(s), a), layout [g][r][i][x][n]
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int gi = 0; gi < (int)c->ngal; ++gi)
+      for (int i = 0; i < (int)L; ++i) {
+        std::vector<int32_t> ee, sg;
+        sample_cbd(seed, KIND_GK_E, (uint64_t)gi * L + i, n, ee);
+        automorph_int(s, c->gal[gi], n, sg);
+        std::vector<uint32_t> a(n), ev(n), sgv(n);
+        for (uint32_t r = 0; r <= L; ++r) {
+          const uint32_t m = c->q[r];
+          sample_uniform(seed, KIND_GK_A, ((uint64_t)gi * L + i) * (L + 1) + r, m, n, a.data());
+          host_ntt(c, (int)r, a.data(), false);
+          for (uint32_t k = 0; k < n; ++k) ev[k] = smod(ee[k], m);
+          host_ntt(c, (int)r, ev.data(), false);
+          const bool diag = (r == (uint32_t)i);
+          if (diag) {
+            for (uint32_t k = 0; k < n; ++k) sgv[k] = smod(sg[k], m);
+            host_ntt(c, (int)r, sgv.data(), false);
+          }
+          const uint64_t Pm = c->P % m;
+          const uint32_t* Sr = &S[(size_t)r * n];
+          uint32_t* kb = &gk->h[((((size_t)gi * (L + 1) + r) * L + i) * 2 + 0) * n];
+          uint32_t* ka = kb + n;
+          for (uint32_t k = 0; k < n; ++k) {
+            uint64_t b = (2ull * m - (uint64_t)a[k] * Sr[k] % m - ev[k]) % m;
+            if (diag) b = (b + Pm * sgv[k]) % m;
+            kb[k] = (uint32_t)b;
+            ka[k] = a[k];
+          }
+        }
+      }
+    std::vector<uint32_t> mont(gk->words);
+    for (size_t x = 0; x < mont.size(); ++x) {
+      const uint32_t r = (uint32_t)((x / ((size_t)L * 2 * n)) % (L + 1));
+      mont[x] = to_mont(gk->h[x], c->mods[r]);
+    }
+    if (dev) {
+      err = hipMalloc((void**)&gk->d, gk->words * 4);
+      if (err == hipSuccess) err = hipMemcpy(gk->d, mont.data(), gk->words * 4, hipMemcpyHostToDevice);
+    }
+  }
+  if (err != hipSuccess) {
+    delete sk;
+    lrhe_pk_destroy(pk);
+    lrhe_gk_destroy(gk);
+    return fail(LRHE_EDEVICE, "key upload: %s", hipGetErrorString(err));
+  }
+  if (sk_out) *sk_out = sk; else delete sk;
+  if (pk_out) *pk_out = pk; else lrhe_pk_destroy(pk);
+  if (gk_out) *gk_out = gk; else lrhe_gk_destroy(gk);
+  return LRHE_OK;
+}
+
+extern "C" void lrhe_sk_destroy(lrhe_sk* sk) { delete sk; }
+extern "C" void lrhe_pk_destroy(lrhe_pk* pk) {
+  if (!pk) return;
+  if (pk->d) (void)hipFree(pk->d);
+  delete pk;
+}
+extern "C" void lrhe_gk_destroy(lrhe_gk* gk) {
+  if (!gk) return;
+  if (gk->d) (void)hipFree(gk->d);
+  delete gk;
+}
+
+extern "C" int lrhe_sk_export(lrhe_ctx* c, const lrhe_sk* sk, int8_t* out) {
+  if (!c || !sk || !out) return fail(LRHE_EINVAL, "null argument");
+  std::copy(sk->s.begin(), sk->s.end(), out);
+  return LRHE_OK;
+}
+extern "C" int lrhe_pk_export(lrhe_ctx* c, const lrhe_pk* pk, uint32_t* out) {
+  if (!c || !pk || !out) return fail(LRHE_EINVAL, "null argument");
+  const uint32_t n = c->n, L = c->L;
+  for (uint32_t x = 0; x < 2 * L; ++x) {
+    std::copy(pk->h.begin() + (size_t)x * n, pk->h.begin() + (size_t)(x + 1) * n, out + (size_t)x * n);
+    host_ntt(c, (int)(x % L), out + (size_t)x * n, true);
+  }
+  return LRHE_OK;
+}
+extern "C" int lrhe_gk_export(lrhe_ctx* c, const lrhe_gk* gk, uint32_t* out) {
+  if (!c || !gk || !out) return fail(LRHE_EINVAL, "null argument");
+  const uint32_t n = c->n, L = c->L;
+  // device/host layout [g][r][i][x][n] -> export layout [g][i][x][r][n]
+#pragma omp parallel for collapse(2)
+  for (int gi = 0; gi < (int)c->ngal; ++gi)
+    for (int r = 0; r <= (int)L; ++r)
+      for (uint32_t i = 0; i < L; ++i)
+        for (uint32_t x = 0; x < 2; ++x) {
+          const uint32_t* src = &gk->h[((((size_t)gi * (L + 1) + r) * L + i) * 2 + x) * n];
+          uint32_t* dst = out + ((((size_t)gi * L + i) * 2 + x) * (L + 1) + r) * n;
+          std::copy(src, src + n, dst);
+          host_ntt(c, r, dst, true);
+        }
+  return LRHE_OK;
+}
+
+// ------------------------------------------------------------------ decryption (client)
+// Little-endian 32-bit limb arithmetic, enough for t x / Q with the exact noise.
+using Big = std::vector<uint32_t>;
+static void big_add_mul(Big& acc, const Big& a, uint64_t m) {   // acc += a m
+  if (acc.size() < a.size() + 3) acc.resize(a.size() + 3, 0);
+  unsigned __int128 carry = 0;
+  size_t i = 0;
+  for (; i < a.size(); ++i) {
+    unsigned __int128 v = (unsigned __int128)a[i] * m + acc[i] + carry;
+    acc[i] = (uint32_t)v;
+    carry = v >> 32;
+  }
+  for (; carry && i < acc.size(); ++i) {
+    unsigned __int128 v = (unsigned __int128)acc[i] + carry;
+    acc[i] = (uint32_t)v;
+    carry = v >> 32;
+  }
+}
+static int big_cmp(const Big& a, const Big& b) {
+  const size_t n = std::max(a.size(), b.size());
+  for (size_t i = n; i-- > 0;) {
+    const uint32_t x = i < a.size() ? a[i] : 0, y = i < b.size() ? b[i] : 0;
+    if (x != y) return x < y ? -1 : 1;
+  }
+  return 0;
+}
+static void big_sub(Big& a, const Big& b) {   // a -= b, a >= b
+  int64_t borrow = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    int64_t v = (int64_t)a[i] - (i < b.size() ? b[i] : 0) - borrow;
+    borrow = v < 0;
+    a[i] = (uint32_t)(v + (borrow << 32));
+  }
+}
+static double big_log2(const Big& a) {
+  for (size_t i = a.size(); i-- > 0;)
+    if (a[i]) {
+      double hi = a[i], lo = i > 0 ? a[i - 1] : 0;
+      return std::log2(hi + lo / 4294967296.0) + 32.0 * i;
+    }
+  return -INFINITY;
+}
+
+static int decrypt_host(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* h, uint32_t count, int64_t* slots,
+                        double* budgets) {
+  const uint32_t n = c->n, L = c->L, t = c->t;
+  const size_t ctw = (size_t)2 * L * n;
+  Big Qhalf = c->Qbig;   // floor(Q / 2)
+  {
+    uint32_t carry = 0;
+    for (size_t i = Qhalf.size(); i-- > 0;) {
+      const uint64_t v = ((uint64_t)carry << 32) | Qhalf[i];
+      Qhalf[i] = (uint32_t)(v >> 1);
+      carry = (uint32_t)(v & 1);
+    }
+  }
+  for (uint32_t ci = 0; ci < count; ++ci) {
+    const uint32_t* C = &h[(size_t)ci * ctw];
+    // x_j = [c0 + c1 s]_{q_j}, coefficient form
+    std::vector<uint32_t> X((size_t)L * n);
+    for (uint32_t j = 0; j < L; ++j) {
+      const uint64_t q = c->q[j];
+      const uint32_t* Sj = &sk->S[(size_t)j * n];
+      uint32_t* xj = &X[(size_t)j * n];
+      for (uint32_t k = 0; k < n; ++k) xj[k] = (uint32_t)((C[(size_t)j * n + k] + (uint64_t)C[(size_t)(L + j) * n + k] * Sj[k]) % q);
+      host_ntt(c, (int)j, xj, true);
+    }
+    // m = sum_j x_j I_j + round(sum_j x_j R_j / q_j) mod t, with the rounding done
+    // exactly: N = sum_j x_j R_j (Q/q_j), k0 = round(N / Q), noise w = N - k0 Q
+    std::vector<uint32_t> mcoef(n);
+    double worst = -INFINITY;
+    for (uint32_t k = 0; k < n; ++k) {
+      uint64_t mi = 0;
+      double approx = 0;
+      Big N;
+      for (uint32_t j = 0; j < L; ++j) {
+        const uint64_t xj = X[(size_t)j * n + k];
+        mi = (mi + xj % t * c->dec_I[j]) % t;
+        approx += (double)xj * c->dec_Rf[j];
+        big_add_mul(N, c->Qhat[j], xj * c->dec_R[j]);
+      }
+      int64_t k0 = (int64_t)std::floor(approx) - 1;
+      if (k0 < 0) k0 = 0;
+      Big K0Q;
+      big_add_mul(K0Q, c->Qbig, (uint64_t)k0);
+      if (big_cmp(N, K0Q) < 0) return fail(LRHE_EINVAL, "decrypt: rounding estimate out of range");
+      big_sub(N, K0Q);   // N - k0 Q >= 0
+      int guard = 0;
+      while (big_cmp(N, Qhalf) > 0 && guard++ < 8) {   // keep |w| <= Q/2
+        if (big_cmp(N, c->Qbig) >= 0) {
+          big_sub(N, c->Qbig);
+          ++k0;
+        } else {   // Q/2 < N < Q: w = N - Q is negative
+          Big tmp = c->Qbig;
+          big_sub(tmp, N);
+          N = tmp;
+          ++k0;
+          break;
+        }
+      }
+      worst = std::max(worst, big_log2(N));
+      mcoef[k] = (uint32_t)((mi + (uint64_t)(k0 % t)) % t);
+    }
+    // decode: slot j = evaluation at psi_t^(e_j)
+    host_ntt(c, (int)L + 1, mcoef.data(), false);
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint32_t v = mcoef[c->slot_pos[j]];
+      slots[(size_t)ci * n + j] = v > (t - 1) / 2 ? (int64_t)v - t : (int64_t)v;
+    }
+    if (budgets) budgets[ci] = (c->log2Q - 1.0) - worst;
+  }
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_decrypt_slots(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, int64_t* slots,
+                                  double* budgets, void* stream) {
+  if (!c || !sk || !ct || !slots) return fail(LRHE_EINVAL, "null argument");
+  NEED_DEVICE(c);
+  std::vector<uint32_t> h((size_t)count * 2 * c->L * c->n);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(h.data(), ct, h.size() * 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return decrypt_host(c, sk, h.data(), count, slots, budgets);
+}
+
+extern "C" int lrhe_decrypt_slots_host(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* ct, uint32_t count,
+                                       int64_t* slots, double* budgets) {
+  if (!c || !sk || !ct || !slots) return fail(LRHE_EINVAL, "null argument");
+  return decrypt_host(c, sk, ct, count, slots, budgets);
+}
+
+extern "C" int lrhe_host_transform(lrhe_ctx* c, uint32_t mod_index, uint32_t* a, int inverse) {
+  if (!c || !a || mod_index > c->L + 1) return fail(LRHE_EINVAL, "bad argument");
+  host_ntt(c, (int)mod_index, a, inverse != 0);
+  return LRHE_OK;
+}
+
+// ------------------------------------------------------------------ device calls
+extern "C" int lrhe_workspace_bytes(const lrhe_ctx* c, int op, uint32_t rows, uint32_t f, uint32_t classes,
+                                    uint64_t* bytes) {
+  if (!c || !bytes) return fail(LRHE_EINVAL, "null argument");
+  const uint64_t K = (f + c->n - 1) / c->n;
+  switch (op) {
+    case LRHE_WS_ENCRYPT_ROWS: *bytes = encrypt_ws_bytes(c, (uint64_t)rows * K); break;
+    case LRHE_WS_ENCRYPT_COLS: *bytes = encrypt_ws_bytes(c, f); break;
+    case LRHE_WS_MATMUL_FAST: *bytes = fast_ws_layout(c, rows * classes, classes).total; break;
+    case LRHE_WS_MATMUL_STANDARD: *bytes = 0; break;
+    default: return fail(LRHE_EINVAL, "unknown workspace op %d", op);
+  }
+  return LRHE_OK;
+}
+
+static int encrypt_common(lrhe_ctx* c, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f, bool cols,
+                          uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!c || !pk || !X || !ct_out) return fail(LRHE_EINVAL, "null argument");
+  if (rows == 0 || f == 0) return fail(LRHE_EINVAL, "empty feature matrix");
+  if (cols && rows > c->n) return fail(LRHE_EINVAL, "standard layout: rows %u > n %u", rows, c->n);
+  const uint64_t K = (f + c->n - 1) / c->n;
+  const uint64_t need = encrypt_ws_bytes(c, cols ? (uint64_t)f : (uint64_t)rows * K);
+  if (!ws || ws_bytes < need) return fail(LRHE_ENOMEM, "workspace %zu < %llu bytes", ws_bytes, (unsigned long long)need);
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_encrypt(c, pk->d, X, rows, f, cols, seed, id0, ct_out, ws, (hipStream_t)stream));
+  return LRHE_OK;
+}
+extern "C" int lrhe_encrypt_rows(lrhe_ctx* c, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f,
+                                 uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  return encrypt_common(c, pk, X, rows, f, false, seed, id0, ct_out, ws, ws_bytes, stream);
+}
+extern "C" int lrhe_encrypt_cols(lrhe_ctx* c, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f,
+                                 uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  return encrypt_common(c, pk, X, rows, f, true, seed, id0, ct_out, ws, ws_bytes, stream);
+}
+
+extern "C" int lrhe_model_create(lrhe_ctx* c, const int64_t* W, const int64_t* bias, uint32_t f, uint32_t classes,
+                                 void* stream, lrhe_model** out) {
+  if (!c || !W || !out) return fail(LRHE_EINVAL, "null argument");
+  if (f == 0 || classes == 0) return fail(LRHE_EINVAL, "empty model");
+  *out = nullptr;
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  auto* m = new lrhe_model();
+  m->f = f;
+  m->classes = classes;
+  m->K = (f + c->n - 1) / c->n;
+  const uint32_t L = c->L, n = c->n;
+  std::vector<uint32_t> db((size_t)classes * L);
+  for (uint32_t j = 0; j < classes; ++j) {
+    const uint32_t b = bias ? smod(bias[j], c->t) : 0;
+    // Delta(b) = floor(Q/t) b + round((Q mod t) b / t)
+    const uint64_t rnd = ((uint64_t)c->dc.qmodt * b + (c->t - 1) / 2) / c->t;
+    for (uint32_t i = 0; i < L; ++i) {
+      const Mod& md = c->mods[i];
+      const uint32_t a = red1(mulm(b, c->dc.qdivt_m[i], md.q, md.qinv), md.q);
+      db[(size_t)j * L + i] = (uint32_t)((a + rnd % md.q) % md.q);
+    }
+  }
+  hipError_t err = hipMalloc((void**)&m->wpt, (size_t)classes * m->K * L * n * 4);
+  if (err == hipSuccess) err = hipMalloc((void**)&m->wsc, (size_t)f * classes * L * 4);
+  if (err == hipSuccess) err = hipMalloc((void**)&m->dbias, db.size() * 4);
+  if (err == hipSuccess) err = hipMemcpy(m->dbias, db.data(), db.size() * 4, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = launch_model_encode(c, W, f, classes, m->wpt, m->wsc, (hipStream_t)stream);
+  if (err == hipSuccess) err = hipStreamSynchronize((hipStream_t)stream);
+  if (err != hipSuccess) {
+    lrhe_model_destroy(m);
+    return fail(LRHE_EDEVICE, "model encode: %s", hipGetErrorString(err));
+  }
+  *out = m;
+  return LRHE_OK;
+}
+extern "C" void lrhe_model_destroy(lrhe_model* m) {
+  if (!m) return;
+  (void)hipFree(m->wpt);
+  (void)hipFree(m->wsc);
+  (void)hipFree(m->dbias);
+  delete m;
+}
+
+extern "C" int lrhe_matmul_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
+                                uint32_t rows, uint32_t* y_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!c || !gk || !m || !xct || !y_out) return fail(LRHE_EINVAL, "null argument");
+  if (rows == 0) return fail(LRHE_EINVAL, "no rows");
+  const uint64_t npairs = (uint64_t)rows * m->classes;
+  if (npairs > 0xffffffffull) return fail(LRHE_EINVAL, "too many pairs");
+  const FastWs lay = fast_ws_layout(c, (uint32_t)npairs, m->classes);
+  if (!ws || ws_bytes < lay.total) return fail(LRHE_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, lay.total);
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_fast(c, gk->d, m, xct, rows, 0, (uint32_t)npairs, -1, y_out, ws, lay, (hipStream_t)stream));
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_matmul_fast_pairs(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
+                                      uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  if (!c || !gk || !m || !xct || !out) return fail(LRHE_EINVAL, "null argument");
+  if (npairs == 0 || (uint64_t)pair0 + npairs > (uint64_t)rows * m->classes) return fail(LRHE_EINVAL, "pair range");
+  if (!(stage == 0 || stage == 1 || stage == 100 || (stage >= 2 && stage <= (int)c->ngal + 2)))
+    return fail(LRHE_EINVAL, "stage %d", stage);
+  const FastWs lay = fast_ws_layout(c, npairs, m->classes);
+  if (!ws || ws_bytes < lay.total) return fail(LRHE_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, lay.total);
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_fast(c, gk->d, m, xct, rows, pair0, npairs, stage, out, ws, lay, (hipStream_t)stream));
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_matmul_standard(lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (!c || !m || !fct || !y_out) return fail(LRHE_EINVAL, "null argument");
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_standard(c, m, fct, y_out, (hipStream_t)stream));
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_to_coeff(lrhe_ctx* c, const uint32_t* in, uint64_t polys, uint32_t* out, void* stream) {
+  if (!c || !in || !out) return fail(LRHE_EINVAL, "null argument");
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  const uint64_t words = polys * c->L * c->n;
+  if (in != out) HIPCHK(hipMemcpyAsync(out, in, words * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  HIPCHK(launch_ntt(c, out, polys * c->L, c->L, 0, true, (hipStream_t)stream));
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_ntt(lrhe_ctx* c, uint32_t* data, uint64_t polys, int inverse, void* stream) {
+  if (!c || !data) return fail(LRHE_EINVAL, "null argument");
+  NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_ntt(c, data, polys * c->L, c->L, 0, inverse != 0, (hipStream_t)stream));
+  return LRHE_OK;
+}

@@ -1,0 +1,764 @@
+// kernels.hip -- gfx950 kernels of the encrypted logistic-regression path.
+//
+// Every polynomial transform runs inside one workgroup: T = n/32 threads hold
+// 32 residues each in VGPRs, do 5 butterfly stages per pass in registers and
+// exchange through a padded LDS buffer between passes (3 passes at n = 16384).
+// Elementwise steps are fused into the transform kernels' load and store
+// phases so that each residue makes one HBM round trip per step.
+#include <hip/hip_runtime.h>
+
+#include "lrhe_internal.h"
+
+namespace lrhe {
+
+constexpr int LOGE = 5;
+template <int LOGN>
+using Gm = Geom<LOGN, LOGE>;
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t dbrv(uint32_t x, int logn) { return __brev(x) >> (32 - logn); }
+
+// NTT-domain automorphism: output index k holds the input at auto_perm(k), for
+// sigma_g: a(X) -> a(X^g) with evaluations stored at psi^(2 brv(k) + 1).
+__device__ __forceinline__ uint32_t auto_perm(uint32_t k, uint32_t g, int logn) {
+  const uint32_t e = 2 * dbrv(k, logn) + 1;
+  const uint32_t ge = (g * e) & ((2u << logn) - 1);
+  return dbrv((ge - 1) >> 1, logn);
+}
+
+template <class G>
+__device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x) {
+  const int t = threadIdx.x;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) lds[G::pad(G::idx(pfrom, t, e))] = x[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(G::idx(pto, t, e))];
+}
+
+// forward transform: x in pass-0 layout with values < 4q; returns the
+// evaluations in last-pass layout, canonical [0, q)
+template <class G>
+__device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const uint32_t* tw, const Mod& m) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < G::NPASS; ++p) {
+    if (p > 0) xchg<G>(lds, p - 1, p, x);
+    fwd_pass<G>(p, t, x, tw, m.q, m.qinv);
+  }
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = red2(x[e], m.q);
+}
+
+// inverse transform: x in last-pass layout with values < 2q; returns canonical
+// coefficients in pass-0 layout
+template <class G>
+__device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const uint32_t* itw, const Mod& m) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int p = G::NPASS - 1; p >= 0; --p) {
+    if (p < G::NPASS - 1) xchg<G>(lds, p + 1, p, x);
+    inv_pass<G>(p, t, x, itw, m.q, m.qinv);
+  }
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = red1(mulm(x[e], m.ninv_m, m.q, m.qinv), m.q);
+}
+
+// pass-0 layout: element e of thread t is index e T + t (coalesced)
+template <class G>
+__device__ __forceinline__ int idx0(int e) { return e * G::T + threadIdx.x; }
+// last-pass layout index
+template <class G>
+__device__ __forceinline__ int idxL(int e) { return G::idx(G::NPASS - 1, threadIdx.x, e); }
+
+template <class G>
+__device__ __forceinline__ void load0(const uint32_t* __restrict__ g, uint32_t* x) {
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = g[idx0<G>(e)];
+}
+template <class G>
+__device__ __forceinline__ void store0(uint32_t* __restrict__ g, const uint32_t* x) {
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) g[idx0<G>(e)] = x[e];
+}
+// last-pass layout: contiguous chunks of 2^r_last residues; vector access when possible
+template <class G>
+__device__ __forceinline__ void loadL(const uint32_t* __restrict__ g, uint32_t* x) {
+  constexpr int C = 1 << G::r(G::NPASS - 1);
+  if constexpr (C % 4 == 0) {
+#pragma unroll
+    for (int e = 0; e < G::E; e += 4) {
+      const uint4 v = *reinterpret_cast<const uint4*>(g + idxL<G>(e));
+      x[e] = v.x; x[e + 1] = v.y; x[e + 2] = v.z; x[e + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = g[idxL<G>(e)];
+  }
+}
+template <class G>
+__device__ __forceinline__ void storeL(uint32_t* __restrict__ g, const uint32_t* x) {
+  constexpr int C = 1 << G::r(G::NPASS - 1);
+  if constexpr (C % 4 == 0) {
+#pragma unroll
+    for (int e = 0; e < G::E; e += 4)
+      *reinterpret_cast<uint4*>(g + idxL<G>(e)) = make_uint4(x[e], x[e + 1], x[e + 2], x[e + 3]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) g[idxL<G>(e)] = x[e];
+  }
+}
+
+// lazy accumulate: a, v in [0, 2q) -> [0, 2q)
+__device__ __forceinline__ uint32_t acc2(uint32_t a, uint32_t v, uint32_t q) {
+  const uint32_t s = a + v;
+  return umin(s, s - 2 * q);
+}
+
+// ------------------------------------------------------------------ batched transform
+template <int LOGN, bool INV>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_ntt(DevCtx c, uint32_t* data, uint32_t nmod, uint32_t mod0) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const size_t p = blockIdx.x;
+  const int mi = mod0 + (int)(p % nmod);
+  uint32_t* g = data + p * G::N;
+  uint32_t x[G::E];
+  if (!INV) {
+    load0<G>(g, x);
+    ntt_fwd<G>(x, lds, c.tw + (size_t)mi * G::N, c.mod[mi]);
+    storeL<G>(g, x);
+  } else {
+    loadL<G>(g, x);
+    ntt_inv<G>(x, lds, c.itw + (size_t)mi * G::N, c.mod[mi]);
+    store0<G>(g, x);
+  }
+}
+
+// ------------------------------------------------------------------ encoding mod t
+// Source of slot values for the batch encoder.
+enum EncSrc { SRC_ROWS = 0, SRC_COLS = 1, SRC_WT = 2 };
+
+__device__ __forceinline__ uint32_t mod_t_i64(int64_t v, uint32_t t) {
+  int64_t r = v % (int64_t)t;
+  return (uint32_t)(r < 0 ? r + t : r);
+}
+
+// plaintext poly ci (coefficients mod t, canonical, natural order) from slot
+// values; rows: ci = i K + k -> X[i][k n + s]; cols: ci = k -> X[s][k] (s < rows);
+// wt: ci = j K + k -> W[k n + s][j] (W is f x classes).  Also writes
+// rnd[ci][k] = round((Q mod t) m_k / t) for the encryption's Delta(m).
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_encode(DevCtx c, const int64_t* __restrict__ src, int mode,
+                                                        uint32_t rows, uint32_t f, uint32_t K, uint32_t classes,
+                                                        uint32_t* __restrict__ m_out, uint32_t* __restrict__ rnd) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const size_t ci = blockIdx.x;
+  const uint32_t t = c.t;
+  uint32_t x[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const uint32_t s = c.pos_slot[idxL<G>(e)];
+    int64_t v = 0;
+    if (mode == SRC_ROWS) {
+      const uint64_t i = ci / K, k = ci % K, col = k * G::N + s;
+      if (col < f) v = src[i * f + col];
+    } else if (mode == SRC_COLS) {
+      if (s < rows) v = src[(size_t)s * f + ci];
+    } else {
+      const uint64_t j = ci / K, k = ci % K, row = k * G::N + s;
+      if (row < f) v = src[row * classes + j];
+    }
+    x[e] = mod_t_i64(v, t);
+  }
+  const int mt = c.L + 1;
+  ntt_inv<G>(x, lds, c.itw + (size_t)mt * G::N, c.mod[mt]);
+  store0<G>(m_out + ci * G::N, x);
+  if (rnd) {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+      const uint64_t y = (uint64_t)c.qmodt * x[e] + (t - 1) / 2;
+      uint64_t qd = (uint64_t)((double)y / (double)t);
+      if (qd * t > y) --qd;
+      else if ((qd + 1) * t <= y) ++qd;
+      rnd[ci * G::N + idx0<G>(e)] = (uint32_t)qd;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ encryption
+// u (ternary), e0, e1 (CBD eta = 21) of ciphertext ci, 16 coefficients per thread.
+__global__ __launch_bounds__(256) void k_sample(uint64_t seed, uint64_t id0, uint32_t n, uint64_t nct,
+                                                int8_t* __restrict__ small) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t per = n / 16;
+  const uint64_t ci = gid / per;
+  const uint32_t grp = (uint32_t)(gid % per);
+  if (ci >= nct) return;
+  const uint64_t id = id0 + ci;
+  int8_t* u = small + ci * 3 * n;
+  int8_t* e0 = u + n;
+  int8_t* e1 = e0 + n;
+  uint32_t w[16];
+  chacha20(seed, KIND_ENC_U, id, grp, w);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) u[16 * grp + k] = (int8_t)ternary_of(w[k]);
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    chacha20(seed, KIND_ENC_E0, id, 2 * grp + half, w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e0[16 * grp + 8 * half + k] = (int8_t)cbd21_of(w[2 * k], w[2 * k + 1]);
+    chacha20(seed, KIND_ENC_E1, id, 2 * grp + half, w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e1[16 * grp + 8 * half + k] = (int8_t)cbd21_of(w[2 * k], w[2 * k + 1]);
+  }
+}
+
+__device__ __forceinline__ uint32_t small_mod(int v, uint32_t q) { return v < 0 ? q + v : (uint32_t)v; }
+
+// ct = (pk0 U + NTT(e0 + Delta(m)), pk1 U + NTT(e1)) for ciphertext ci, limb j
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_t* __restrict__ pk,
+                                                         const int8_t* __restrict__ small,
+                                                         const uint32_t* __restrict__ m,
+                                                         const uint32_t* __restrict__ rnd,
+                                                         uint32_t* __restrict__ ct) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const size_t ci = blockIdx.x / c.L;
+  const int j = blockIdx.x % c.L;
+  const Mod md = c.mod[j];
+  const uint32_t* tw = c.tw + (size_t)j * G::N;
+  const int8_t* su = small + ci * 3 * G::N;
+  uint32_t U[G::E], x[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) U[e] = small_mod(su[idx0<G>(e)], md.q);
+  ntt_fwd<G>(U, lds, tw, md);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const int k = idx0<G>(e);
+    const uint32_t mm = m[ci * G::N + k];
+    const uint32_t delta = addm(red1(mulm(mm, c.qdivt_m[j], md.q, md.qinv), md.q), rnd[ci * G::N + k], md.q);
+    x[e] = addm(small_mod(su[G::N + k], md.q), delta, md.q);
+  }
+  ntt_fwd<G>(x, lds, tw, md);
+  uint32_t* out = ct + ci * 2 * c.L * G::N;
+  const uint32_t* pk0 = pk + (size_t)j * G::N;
+  const uint32_t* pk1 = pk + (size_t)(c.L + j) * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], pk0[idxL<G>(e)], md.q, md.qinv), md.q), x[e], md.q);
+  storeL<G>(out + (size_t)j * G::N, x);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = small_mod(su[2 * G::N + idx0<G>(e)], md.q);
+  ntt_fwd<G>(x, lds, tw, md);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], pk1[idxL<G>(e)], md.q, md.qinv), md.q), x[e], md.q);
+  storeL<G>(out + (size_t)(c.L + j) * G::N, x);
+}
+
+// ------------------------------------------------------------------ model encoding
+// centred lift of a residue mod t into q, Montgomery form
+__device__ __forceinline__ uint32_t lift_mont(uint32_t v, uint32_t t, const Mod& md) {
+  const uint32_t l = v > (t - 1) / 2 ? v + md.q - t : v;
+  return to_mont(l, md);
+}
+
+// weight plaintext (class j, chunk k) in limb i: lift, Montgomery form, transform
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_lift_ntt(DevCtx c, const uint32_t* __restrict__ mt,
+                                                          uint32_t* __restrict__ out) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const size_t pi = blockIdx.x / c.L;
+  const int i = blockIdx.x % c.L;
+  const Mod md = c.mod[i];
+  uint32_t x[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = lift_mont(mt[pi * G::N + idx0<G>(e)], c.t, md);
+  ntt_fwd<G>(x, lds, c.tw + (size_t)i * G::N, md);
+  storeL<G>(out + (pi * c.L + i) * G::N, x);
+}
+
+// scalar weights for the standard baseline: wsc[k][j][i] = lift(W[k][j] mod t) R mod q_i
+__global__ void k_scalars(DevCtx c, const int64_t* __restrict__ W, uint64_t count, uint32_t* __restrict__ wsc) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count * c.L) return;
+  const uint64_t kj = g / c.L;
+  const int i = (int)(g % c.L);
+  wsc[g] = lift_mont(mod_t_i64(W[kj], c.t), c.t, c.mod[i]);
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+// chunk products and add_many: out[p][x][j] = sum_k X^[i][k][x][j] W-[jc][k][j]
+__global__ __launch_bounds__(256) void k_mac(DevCtx c, const uint32_t* __restrict__ xct,
+                                             const uint32_t* __restrict__ wpt, uint32_t K, uint32_t classes,
+                                             uint32_t pb, uint32_t B, uint32_t* __restrict__ out) {
+  const uint32_t n = c.n, L = c.L;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one uint4 each
+  const uint64_t per_pair = (uint64_t)2 * L * n / 4;
+  const uint64_t lp = gid / per_pair;
+  if (lp >= B) return;
+  const uint64_t w4 = gid % per_pair;
+  const uint64_t word = w4 * 4;
+  const uint32_t xpoly = (uint32_t)(word / ((uint64_t)L * n));
+  const uint32_t j = (uint32_t)((word / n) % L);
+  const uint32_t k0 = (uint32_t)(word % n);
+  const uint64_t r = pb + lp, i = r / classes, jc = r % classes;
+  const Mod md = c.mod[j];
+  uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint4 xv = *reinterpret_cast<const uint4*>(xct + (((i * K + k) * 2 + xpoly) * L + j) * n + k0);
+    const uint4 wv = *reinterpret_cast<const uint4*>(wpt + ((jc * K + k) * L + j) * n + k0);
+    a0 += (uint64_t)xv.x * wv.x; a1 += (uint64_t)xv.y * wv.y;
+    a2 += (uint64_t)xv.z * wv.z; a3 += (uint64_t)xv.w * wv.w;
+    if ((k % 8) == 7 || k + 1 == K) {   // at most 8 products below q 2^32 + slack
+      s0 = addm(s0, red2(redc(a0, md.q, md.qinv), md.q), md.q);
+      s1 = addm(s1, red2(redc(a1, md.q, md.qinv), md.q), md.q);
+      s2 = addm(s2, red2(redc(a2, md.q, md.qinv), md.q), md.q);
+      s3 = addm(s3, red2(redc(a3, md.q, md.qinv), md.q), md.q);
+      a0 = a1 = a2 = a3 = 0;
+    }
+  }
+  *reinterpret_cast<uint4*>(out + lp * 2 * L * n + word) = make_uint4(s0, s1, s2, s3);
+}
+
+// key switch, part 1: d_i = INTT(sigma_g(c1))_i, digits in coefficient form
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_intt(DevCtx c, const uint32_t* __restrict__ cin, uint32_t g,
+                                                         uint32_t* __restrict__ D) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const size_t lp = blockIdx.x / c.L;
+  const int i = blockIdx.x % c.L;
+  const uint32_t* src = cin + (lp * 2 * c.L + c.L + i) * G::N;
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const int k = idx0<G>(e);
+    lds[G::pad(k)] = src[k];
+  }
+  __syncthreads();
+  uint32_t x[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(idxL<G>(e), g, LOGN))];
+  ntt_inv<G>(x, lds, c.itw + (size_t)i * G::N, c.mod[i]);
+  store0<G>(D + (lp * c.L + i) * G::N, x);
+}
+
+// key switch, part 2: for target modulus r, acc_x = sum_i NTT_r(d_i) ksk_{g,i,x,r};
+// r = P additionally returns rho_x = [INTT(acc_x) + (P-1)/2]_P in coefficient form
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_mac(DevCtx c, const uint32_t* __restrict__ D,
+                                                        const uint32_t* __restrict__ key,
+                                                        uint32_t* __restrict__ ACC) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const int L = c.L;
+  const size_t lp = blockIdx.x / (L + 1);
+  const int r = blockIdx.x % (L + 1);
+  const Mod mr = c.mod[r];
+  const uint32_t* tw = c.tw + (size_t)r * G::N;
+  const uint32_t* kr = key + (size_t)r * L * 2 * G::N;   // [L digits][2][n]
+  uint32_t ab[G::E], aa[G::E], x[G::E];
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) ab[e] = aa[e] = 0;
+  for (int i = 0; i < L; ++i) {
+    load0<G>(D + (lp * L + i) * G::N, x);   // d_i < q_i < 4 q_r: a valid lazy input
+    ntt_fwd<G>(x, lds, tw, mr);
+    const uint32_t* kb = kr + (size_t)(2 * i) * G::N;
+    const uint32_t* ka = kb + G::N;
+    uint32_t vb[G::E], va[G::E];
+    loadL<G>(kb, vb);
+    loadL<G>(ka, va);
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+      ab[e] = acc2(ab[e], mulm(x[e], vb[e], mr.q, mr.qinv), mr.q);
+      aa[e] = acc2(aa[e], mulm(x[e], va[e], mr.q, mr.qinv), mr.q);
+    }
+  }
+  uint32_t* out = ACC + (lp * (L + 1) + r) * 2 * G::N;
+  if (r < L) {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) { ab[e] = red1(ab[e], mr.q); aa[e] = red1(aa[e], mr.q); }
+    storeL<G>(out, ab);
+    storeL<G>(out + G::N, aa);
+  } else {
+    const uint32_t h = (mr.q - 1) / 2;
+    ntt_inv<G>(ab, lds, c.itw + (size_t)r * G::N, mr);
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) ab[e] = addm(ab[e], h, mr.q);
+    store0<G>(out, ab);
+    ntt_inv<G>(aa, lds, c.itw + (size_t)r * G::N, mr);
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) aa[e] = addm(aa[e], h, mr.q);
+    store0<G>(out + G::N, aa);
+  }
+}
+
+// key switch, part 3: rounded division by P, coefficient-wise
+// round(acc / P) = (acc - [acc]_P) / P with [acc]_P the centred residue
+// rho_x - h, so out_x = (acc_x - NTT(rho_x - h)) P^-1 mod q_j; then the
+// rotate-and-accumulate c0' = c0 + sigma_g(c0) + out_b, c1' = c1 + out_a
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_moddown(DevCtx c, const uint32_t* __restrict__ cin,
+                                                            const uint32_t* __restrict__ ACC, uint32_t g,
+                                                            uint32_t* __restrict__ cout) {
+  using G = Gm<LOGN>;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const int L = c.L;
+  const size_t lp = blockIdx.x / L;
+  const int j = blockIdx.x % L;
+  const Mod md = c.mod[j];
+  const uint32_t* tw = c.tw + (size_t)j * G::N;
+  const uint32_t* acc = ACC + (lp * (L + 1) + j) * 2 * G::N;
+  const uint32_t* rho = ACC + (lp * (L + 1) + L) * 2 * G::N;
+  const uint32_t* c0 = cin + (lp * 2 * L + j) * G::N;
+  const uint32_t* c1 = cin + (lp * 2 * L + L + j) * G::N;
+  uint32_t x[G::E], a[G::E];
+  const uint32_t hq = c.hmod[j], pinv = c.pinv_m[j];
+  // b part: rho - h + q_j < P + q_j < 4 q_j is a valid lazy input
+  load0<G>(rho, x);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] += md.q - hq;
+  ntt_fwd<G>(x, lds, tw, md);
+  loadL<G>(acc, a);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const int k = idxL<G>(e);
+    const uint32_t ob = red1(mulm(a[e] + md.q - x[e], pinv, md.q, md.qinv), md.q);
+    x[e] = addm(addm(c0[k], c0[auto_perm(k, g, LOGN)], md.q), ob, md.q);
+  }
+  storeL<G>(cout + (lp * 2 * L + j) * G::N, x);
+  // a part
+  load0<G>(rho + G::N, x);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] += md.q - hq;
+  ntt_fwd<G>(x, lds, tw, md);
+  loadL<G>(acc + G::N, a);
+  uint32_t cc[G::E];
+  loadL<G>(c1, cc);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const uint32_t oa = red1(mulm(a[e] + md.q - x[e], pinv, md.q, md.qinv), md.q);
+    x[e] = addm(cc[e], oa, md.q);
+  }
+  storeL<G>(cout + (lp * 2 * L + L + j) * G::N, x);
+}
+
+// bias + one-hot mask of each pair, accumulated per group of G pairs (the
+// compression of Algorithm 1 is a modular sum, so partial sums are exact).
+// mode 0: accumulate into part[group]; mode 1: write each masked pair to
+// out[lp]; mode 2: write each pair with the bias only (no mask) to out[lp].
+template <int LOGN>
+__global__ __launch_bounds__(Gm<LOGN>::T) void k_mask(DevCtx c, const uint32_t* __restrict__ cin,
+                                                      const uint32_t* __restrict__ dbias, uint32_t classes,
+                                                      uint32_t pb, uint32_t B, uint32_t Gp, uint32_t gbase,
+                                                      int mode, uint32_t* __restrict__ out) {
+  using Gg = Gm<LOGN>;
+  __shared__ uint32_t lds[Gg::LDS_WORDS];
+  const int L = c.L;
+  const uint32_t grp = blockIdx.x / L;
+  const int j = blockIdx.x % L;
+  const Mod md = c.mod[j];
+  const uint32_t* tw = c.tw + (size_t)j * Gg::N;
+  const uint32_t twon_mask = 2 * Gg::N - 1;
+  uint32_t a0[Gg::E], a1[Gg::E], x[Gg::E];
+#pragma unroll
+  for (int e = 0; e < Gg::E; ++e) a0[e] = a1[e] = 0;
+  const uint32_t lp0 = grp * Gp, lp1 = min(lp0 + Gp, B);
+  for (uint32_t lp = lp0; lp < lp1; ++lp) {
+    const uint64_t r = (uint64_t)pb + lp;
+    const uint32_t jc = (uint32_t)(r % classes);
+    const uint32_t l = (uint32_t)(r % Gg::N);
+    const uint32_t bj = dbias[jc * L + j];
+    const uint32_t* c0 = cin + ((size_t)lp * 2 * L + j) * Gg::N;
+    const uint32_t* c1 = c0 + (size_t)L * Gg::N;
+    if (mode == 2) {
+      uint32_t* o = out + (size_t)lp * 2 * L * Gg::N;
+#pragma unroll
+      for (int e = 0; e < Gg::E; ++e) {
+        const int k = idx0<Gg>(e);
+        o[(size_t)j * Gg::N + k] = addm(c0[k], bj, md.q);
+        o[(size_t)(L + j) * Gg::N + k] = c1[k];
+      }
+      continue;
+    }
+    const uint32_t el = c.slot_exp[l];
+#pragma unroll
+    for (int e = 0; e < Gg::E; ++e) x[e] = lift_mont(c.mask_tab[(el * (uint32_t)idx0<Gg>(e)) & twon_mask], c.t, md);
+    ntt_fwd<Gg>(x, lds, tw, md);
+    uint32_t v0[Gg::E], v1[Gg::E];
+    loadL<Gg>(c0, v0);
+    loadL<Gg>(c1, v1);
+#pragma unroll
+    for (int e = 0; e < Gg::E; ++e) {
+      v0[e] = mulm(addm(v0[e], bj, md.q), x[e], md.q, md.qinv);
+      v1[e] = mulm(v1[e], x[e], md.q, md.qinv);
+    }
+    if (mode == 1) {
+      uint32_t* o = out + (size_t)lp * 2 * L * Gg::N;
+#pragma unroll
+      for (int e = 0; e < Gg::E; ++e) { v0[e] = red1(v0[e], md.q); v1[e] = red1(v1[e], md.q); }
+      storeL<Gg>(o + (size_t)j * Gg::N, v0);
+      storeL<Gg>(o + (size_t)(L + j) * Gg::N, v1);
+    } else {
+#pragma unroll
+      for (int e = 0; e < Gg::E; ++e) { a0[e] = acc2(a0[e], v0[e], md.q); a1[e] = acc2(a1[e], v1[e], md.q); }
+    }
+  }
+  if (mode == 0) {
+    uint32_t* o = out + (size_t)(gbase + grp) * 2 * L * Gg::N;
+#pragma unroll
+    for (int e = 0; e < Gg::E; ++e) { a0[e] = red1(a0[e], md.q); a1[e] = red1(a1[e], md.q); }
+    storeL<Gg>(o + (size_t)j * Gg::N, a0);
+    storeL<Gg>(o + (size_t)(L + j) * Gg::N, a1);
+  }
+}
+
+// compression: y[m] = sum of the partial sums of the groups whose pairs land in output m
+__global__ __launch_bounds__(256) void k_compress(DevCtx c, const uint32_t* __restrict__ part, uint32_t ngroups,
+                                                  uint32_t groups_per_out, uint32_t nout,
+                                                  uint32_t* __restrict__ y) {
+  const uint32_t n = c.n, L = c.L;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t ctw = (uint64_t)2 * L * n;
+  if (gid >= nout * ctw / 4) return;
+  const uint64_t word = gid * 4;
+  const uint32_t m = (uint32_t)(word / ctw);
+  const uint64_t w = word % ctw;
+  const uint32_t j = (uint32_t)((w / n) % L);
+  const uint32_t q = c.mod[j].q;
+  uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  const uint32_t g0 = m * groups_per_out, g1 = min(g0 + groups_per_out, ngroups);
+  for (uint32_t g = g0; g < g1; ++g) {
+    const uint4 v = *reinterpret_cast<const uint4*>(part + g * ctw + w);
+    s0 = addm(s0, v.x, q); s1 = addm(s1, v.y, q); s2 = addm(s2, v.z, q); s3 = addm(s3, v.w, q);
+  }
+  *reinterpret_cast<uint4*>(y + m * ctw + w) = make_uint4(s0, s1, s2, s3);
+}
+
+// ------------------------------------------------------------------ standard baseline
+// y[j][x][i] = sum_k fct[k][x][i] w_kj (+ Delta(b_j) for x = 0); one residue per thread,
+// classes in chunks of 16 held in registers, so every input residue is read once per chunk.
+__global__ __launch_bounds__(256) void k_std(DevCtx c, const uint32_t* __restrict__ fct,
+                                             const uint32_t* __restrict__ wsc, const uint32_t* __restrict__ dbias,
+                                             uint32_t f, uint32_t classes, uint32_t* __restrict__ y) {
+  const uint32_t n = c.n, L = c.L;
+  const uint64_t ctw = (uint64_t)2 * L * n;
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // word within a ciphertext
+  if (w >= ctw) return;
+  const uint32_t xpoly = (uint32_t)(w / ((uint64_t)L * n));
+  const uint32_t i = (uint32_t)((w / n) % L);
+  const Mod md = c.mod[i];
+  for (uint32_t j0 = 0; j0 < classes; j0 += 16) {
+    const uint32_t nj = min(16u, classes - j0);
+    uint64_t acc[16];
+    uint32_t s[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) { acc[jj] = 0; s[jj] = 0; }
+    for (uint32_t k = 0; k < f; ++k) {
+      const uint32_t v = fct[(uint64_t)k * ctw + w];
+      const uint32_t* wk = wsc + ((uint64_t)k * classes + j0) * L + i;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj)
+        if (jj < (int)nj) acc[jj] += (uint64_t)v * wk[(size_t)jj * L];
+      if ((k % 8) == 7 || k + 1 == f) {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+          s[jj] = addm(s[jj], red2(redc(acc[jj], md.q, md.qinv), md.q), md.q);
+          acc[jj] = 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      if (jj < (int)nj) {
+        uint32_t v = s[jj];
+        if (xpoly == 0) v = addm(v, dbias[(j0 + jj) * L + i], md.q);
+        y[(uint64_t)(j0 + jj) * ctw + w] = v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define LRHE_DISPATCH(LOGNVAR, ...)                          \
+  switch (LOGNVAR) {                                         \
+    case 10: { constexpr int LN = 10; __VA_ARGS__; } break; \
+    case 11: { constexpr int LN = 11; __VA_ARGS__; } break; \
+    case 12: { constexpr int LN = 12; __VA_ARGS__; } break; \
+    case 13: { constexpr int LN = 13; __VA_ARGS__; } break; \
+    case 14: { constexpr int LN = 14; __VA_ARGS__; } break; \
+    case 15: { constexpr int LN = 15; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                    \
+  }
+
+static inline unsigned blocks_for(uint64_t threads, unsigned bs) { return (unsigned)((threads + bs - 1) / bs); }
+
+hipError_t launch_ntt(const lrhe_ctx* c, uint32_t* data, uint64_t npolys, uint32_t nmod, uint32_t mod0, bool inverse,
+                      hipStream_t s) {
+  if (npolys == 0) return hipSuccess;
+  LRHE_DISPATCH(c->logn, {
+    ProfScope ps(s, inverse ? "k_ntt_inv" : "k_ntt_fwd");
+    if (inverse) k_ntt<LN, true><<<(unsigned)npolys, Gm<LN>::T, 0, s>>>(c->dc, data, nmod, mod0);
+    else k_ntt<LN, false><<<(unsigned)npolys, Gm<LN>::T, 0, s>>>(c->dc, data, nmod, mod0);
+  });
+  return hipGetLastError();
+}
+
+size_t encrypt_ws_bytes(const lrhe_ctx* c, uint64_t nct) {
+  // small (3 n int8) + m (n u32) + rnd (n u32), 256-byte aligned pieces
+  const uint64_t n = c->n;
+  auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
+  return al(nct * 3 * n) + al(nct * n * 4) * 2;
+}
+
+hipError_t launch_encrypt(const lrhe_ctx* c, const uint32_t* pk_d, const int64_t* X, uint32_t rows, uint32_t f,
+                          bool cols, uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, hipStream_t s) {
+  const uint64_t n = c->n;
+  const uint32_t K = (uint32_t)((f + n - 1) / n);
+  const uint64_t nct = cols ? f : (uint64_t)rows * K;
+  if (nct == 0) return hipSuccess;
+  auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
+  int8_t* small = (int8_t*)ws;
+  uint32_t* m = (uint32_t*)((char*)ws + al(nct * 3 * n));
+  uint32_t* rnd = (uint32_t*)((char*)m + al(nct * n * 4));
+  {
+    ProfScope ps(s, "k_sample");
+    k_sample<<<blocks_for(nct * (n / 16), 256), 256, 0, s>>>(seed, id0, (uint32_t)n, nct, small);
+  }
+  LRHE_DISPATCH(c->logn, {
+    { ProfScope ps(s, "k_encode");
+      k_encode<LN><<<(unsigned)nct, Gm<LN>::T, 0, s>>>(c->dc, X, cols ? SRC_COLS : SRC_ROWS, rows, f, K, 0, m, rnd); }
+    { ProfScope ps(s, "k_encrypt");
+      k_encrypt<LN><<<(unsigned)(nct * c->L), Gm<LN>::T, 0, s>>>(c->dc, pk_d, small, m, rnd, ct_out); }
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_model_encode(const lrhe_ctx* c, const int64_t* W, uint32_t f, uint32_t classes, uint32_t* wpt,
+                               uint32_t* wsc, hipStream_t s) {
+  const uint64_t n = c->n;
+  const uint32_t K = (uint32_t)((f + n - 1) / n);
+  const uint64_t npt = (uint64_t)classes * K;
+  uint32_t* mt = nullptr;
+  hipError_t err = hipMallocAsync((void**)&mt, npt * n * 4, s);
+  if (err != hipSuccess) return err;
+  LRHE_DISPATCH(c->logn, {
+    k_encode<LN><<<(unsigned)npt, Gm<LN>::T, 0, s>>>(c->dc, W, SRC_WT, 0, f, K, classes, mt, nullptr);
+    k_lift_ntt<LN><<<(unsigned)(npt * c->L), Gm<LN>::T, 0, s>>>(c->dc, mt, wpt);
+  });
+  const uint64_t cnt = (uint64_t)f * classes;
+  k_scalars<<<blocks_for(cnt * c->L, 256), 256, 0, s>>>(c->dc, W, cnt, wsc);
+  err = hipGetLastError();
+  (void)hipFreeAsync(mt, s);
+  return err;
+}
+
+FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes) {
+  (void)classes;
+  FastWs w{};
+  const uint64_t n = c->n, L = c->L;
+  const uint64_t ctb = 2 * L * n * 4;
+  // pairs per compression group: a power of two dividing n, smaller for small jobs
+  uint32_t G = 32;
+  while (G > 1 && (uint64_t)G * 64 > npairs) G >>= 1;
+  w.G = G;
+  uint32_t B = npairs < 4096 ? npairs : 4096;
+  B = (B + G - 1) / G * G;
+  if (B == 0) B = G;
+  w.B = B;
+  auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
+  const uint64_t ngroups = (npairs + G - 1) / G;
+  size_t off = 0;
+  w.cA = off; off += al(B * ctb);
+  w.cB = off; off += al(B * ctb);
+  w.D = off; off += al(B * L * n * 4);
+  w.ACC = off; off += al(B * (L + 1) * 2 * n * 4);
+  w.part = off; off += al(ngroups * ctb);
+  w.total = off;
+  return w;
+}
+
+hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model* m, const uint32_t* xct,
+                       uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out, void* ws,
+                       const FastWs& lay, hipStream_t s) {
+  (void)rows;
+  const uint64_t n = c->n, L = c->L;
+  const uint64_t ctw = 2 * L * n;
+  char* base = (char*)ws;
+  uint32_t* cA = (uint32_t*)(base + lay.cA);
+  uint32_t* cB = (uint32_t*)(base + lay.cB);
+  uint32_t* D = (uint32_t*)(base + lay.D);
+  uint32_t* ACC = (uint32_t*)(base + lay.ACC);
+  uint32_t* part = (uint32_t*)(base + lay.part);
+  const size_t keyw = (size_t)(L + 1) * L * 2 * n;
+  const uint32_t pend = pair0 + npairs;
+  for (uint32_t pb = pair0; pb < pend; pb += lay.B) {
+    const uint32_t Bt = min(lay.B, pend - pb);
+    uint32_t* cur = cA;
+    uint32_t* nxt = cB;
+    {
+      ProfScope ps(s, "k_mac");
+      k_mac<<<blocks_for((uint64_t)Bt * ctw / 4, 256), 256, 0, s>>>(c->dc, xct, m->wpt, m->K, m->classes, pb, Bt,
+                                                                     cur);
+    }
+    if (stage == 1) {
+      (void)hipMemcpyAsync(out + (uint64_t)(pb - pair0) * ctw, cur, (uint64_t)Bt * ctw * 4, hipMemcpyDeviceToDevice, s);
+      continue;
+    }
+    const int steps = (stage >= 2 && stage < 100) ? stage - 2 : (int)c->ngal;
+    for (int gi = 0; gi < steps; ++gi) {
+      const uint32_t g = c->gal[gi];
+      const uint32_t* key = gk_d + (size_t)gi * keyw;
+      LRHE_DISPATCH(c->logn, {
+        { ProfScope ps(s, "k_ks_intt");
+          k_ks_intt<LN><<<(unsigned)(Bt * L), Gm<LN>::T, 0, s>>>(c->dc, cur, g, D); }
+        { ProfScope ps(s, "k_ks_mac");
+          k_ks_mac<LN><<<(unsigned)(Bt * (L + 1)), Gm<LN>::T, 0, s>>>(c->dc, D, key, ACC); }
+        { ProfScope ps(s, "k_ks_moddown");
+          k_ks_moddown<LN><<<(unsigned)(Bt * L), Gm<LN>::T, 0, s>>>(c->dc, cur, ACC, g, nxt); }
+      });
+      uint32_t* tmp = cur; cur = nxt; nxt = tmp;
+    }
+    if (stage >= 2 && stage < 100) {
+      (void)hipMemcpyAsync(out + (uint64_t)(pb - pair0) * ctw, cur, (uint64_t)Bt * ctw * 4, hipMemcpyDeviceToDevice, s);
+      continue;
+    }
+    if (stage == 0 || stage == 100) {   // per-pair export
+      LRHE_DISPATCH(c->logn, {
+        k_mask<LN><<<(unsigned)(((Bt + lay.G - 1) / lay.G) * L), Gm<LN>::T, 0, s>>>(
+            c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G, 0, stage == 0 ? 1 : 2,
+            out + (uint64_t)(pb - pair0) * ctw);
+      });
+      continue;
+    }
+    // stage < 0: full Algorithm 1, partial compression per group
+    const uint32_t ngt = (Bt + lay.G - 1) / lay.G;
+    LRHE_DISPATCH(c->logn, {
+      ProfScope ps(s, "k_mask");
+      k_mask<LN><<<(unsigned)(ngt * L), Gm<LN>::T, 0, s>>>(c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G,
+                                                             (pb - pair0) / lay.G, 0, part);
+    });
+  }
+  if (stage < 0) {
+    const uint32_t ngroups = (npairs + lay.G - 1) / lay.G;
+    const uint32_t gpo = (uint32_t)(n / lay.G);
+    const uint32_t nout = (uint32_t)((npairs + n - 1) / n);
+    ProfScope ps(s, "k_compress");
+    k_compress<<<blocks_for((uint64_t)nout * ctw / 4, 256), 256, 0, s>>>(c->dc, part, ngroups, gpo, nout, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,
+                           hipStream_t s) {
+  const uint64_t ctw = (uint64_t)2 * c->L * c->n;
+  ProfScope ps(s, "k_std");
+  k_std<<<blocks_for(ctw, 256), 256, 0, s>>>(c->dc, fct, m->wsc, m->dbias, m->f, m->classes, y_out);
+  return hipGetLastError();
+}
+
+}  // namespace lrhe

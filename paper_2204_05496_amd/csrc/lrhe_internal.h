@@ -1,0 +1,117 @@
+// lrhe_internal.h -- context layout shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lrhe.h"
+#include "lrhe_math.h"
+
+#define LRHE_MAXL 15
+#define LRHE_MINLOGN 10
+#define LRHE_MAXLOGN 15
+
+namespace lrhe {
+
+// Plain-old-data view of the context passed by value to every kernel.
+// Modulus index convention: 0..L-1 data primes, L = special prime P, L+1 = t.
+struct DevCtx {
+  uint32_t n, logn, L;
+  Mod mod[LRHE_MAXL + 2];
+  const uint32_t* tw;        // [(L+2)][n] psi^brv(k) R mod m
+  const uint32_t* itw;       // [(L+2)][n] psi^-brv(k) R mod m
+  const uint32_t* pos_slot;  // [n] transform index k -> slot j (mod-t transform)
+  const uint32_t* slot_exp;  // [n] e_j
+  const uint32_t* mask_tab;  // [2n] n^-1 psi_t^-x mod t
+  uint32_t t, qmodt;         // t, Q mod t
+  uint32_t qdivt_m[LRHE_MAXL];  // floor(Q/t) R mod q_i
+  uint32_t pinv_m[LRHE_MAXL];   // P^-1 R mod q_j
+  uint32_t hmod[LRHE_MAXL];     // (P-1)/2 mod q_j
+};
+
+// Offsets into the fast-matmul workspace for a tile of B pairs.
+struct FastWs {
+  uint32_t B;                 // pairs per tile
+  uint32_t G;                 // pairs per compression group
+  size_t cA, cB, D, ACC, part, total;   // byte offsets, total size
+};
+
+}  // namespace lrhe
+
+struct lrhe_ctx {
+  int device = 0;
+  uint32_t n = 0, logn = 0, L = 0, ngal = 0, t = 0, P = 0;
+  std::vector<uint32_t> q;        // L data primes followed by P
+  std::vector<uint32_t> gal;      // Galois elements of the rotate-and-sum
+  std::vector<lrhe::Mod> mods;    // L + 2 entries
+  std::vector<uint32_t> h_tw, h_itw;   // host copies of the tables, [(L+2)][n]
+  std::vector<uint32_t> slot_pos, pos_slot, slot_exp, mask_tab;
+  // device tables
+  uint32_t* d_tw = nullptr;
+  uint32_t* d_itw = nullptr;
+  uint32_t* d_pos_slot = nullptr;
+  uint32_t* d_slot_exp = nullptr;
+  uint32_t* d_mask_tab = nullptr;
+  lrhe::DevCtx dc{};
+  // big-integer constants for decryption, computed at creation
+  std::vector<uint32_t> dec_I;       // floor(t y_j / q_j) mod t
+  std::vector<uint32_t> dec_R;       // t y_j mod q_j, y_j = (Q/q_j)^-1 mod q_j
+  std::vector<double> dec_Rf;        // dec_R / q_j
+  std::vector<std::vector<uint32_t>> Qhat;  // Q / q_j as little-endian 32-bit limbs
+  std::vector<uint32_t> Qbig;        // Q
+  double log2Q = 0;
+};
+
+struct lrhe_sk {
+  uint32_t n = 0, L = 0;
+  std::vector<int8_t> s;        // ternary coefficients
+  std::vector<uint32_t> S;      // [L][n] evaluation form, canonical
+};
+
+struct lrhe_pk {
+  uint32_t* d = nullptr;        // [2][L][n] evaluation form, Montgomery (x R mod q)
+  std::vector<uint32_t> h;      // host copy, canonical evaluation form
+};
+
+struct lrhe_gk {
+  uint32_t* d = nullptr;        // [ngal][L+1 moduli r][L digits i][2][n] evaluation form, Montgomery
+  size_t words = 0;
+  std::vector<uint32_t> h;      // host copy, canonical evaluation form, same layout
+};
+
+struct lrhe_model {
+  uint32_t f = 0, classes = 0, K = 0;
+  uint32_t* wpt = nullptr;      // [classes][K][L][n] evaluation form, Montgomery
+  uint32_t* wsc = nullptr;      // [f][classes][L] centred scalar weights, Montgomery
+  uint32_t* dbias = nullptr;    // [classes][L] Delta(b_j) mod q_i
+};
+
+namespace lrhe {
+// Records HIP events around a kernel launch on its stream while timing is
+// enabled (lrhe_prof_enable); a no-op otherwise.
+struct ProfScope {
+  ProfScope(hipStream_t s, const char* name);
+  ~ProfScope();
+  hipStream_t s_;
+  const char* name_;
+  void* a_ = nullptr;
+  void* b_ = nullptr;
+};
+
+// kernel launchers (kernels.hip); all return a hipError_t
+hipError_t launch_ntt(const lrhe_ctx* c, uint32_t* data, uint64_t npolys, uint32_t nmod, uint32_t mod0, bool inverse,
+                      hipStream_t s);
+hipError_t launch_encrypt(const lrhe_ctx* c, const uint32_t* pk_d, const int64_t* X, uint32_t rows, uint32_t f,
+                          bool cols, uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, hipStream_t s);
+size_t encrypt_ws_bytes(const lrhe_ctx* c, uint64_t nct);
+hipError_t launch_model_encode(const lrhe_ctx* c, const int64_t* W, uint32_t f, uint32_t classes, uint32_t* wpt,
+                               uint32_t* wsc, hipStream_t s);
+FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes);
+hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model* m, const uint32_t* xct,
+                       uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out, void* ws,
+                       const FastWs& lay, hipStream_t s);
+hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,
+                           hipStream_t s);
+}  // namespace lrhe

@@ -1,0 +1,96 @@
+"""ctypes binding of liblrhe.so (include/lrhe.h): argument marshalling only.
+
+Every step of the encrypted path runs in the library's HIP kernels; torch is
+used for device buffers (ciphertexts, inputs, workspaces) and the current HIP
+stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "liblrhe.so")
+
+LRHE_OK, LRHE_EINVAL, LRHE_EPARAM, LRHE_ENOMEM, LRHE_EAGAIN, LRHE_EDEVICE, LRHE_ENOISE = 0, -1, -2, -3, -4, -5, -6
+WS_ENCRYPT_ROWS, WS_ENCRYPT_COLS, WS_MATMUL_FAST, WS_MATMUL_STANDARD = 1, 2, 3, 4
+
+vp = ctypes.c_void_p
+u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
+sz = ctypes.c_size_t
+
+
+class LrheParams(ctypes.Structure):
+    _fields_ = [("n", u32), ("L", u32), ("q", ctypes.POINTER(u32)), ("P", u32), ("t", u32), ("allow_insecure", u32)]
+
+
+class LrheError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lrhe error {code}: {msg}")
+        self.code = code
+
+
+# name -> (restype, argtypes); mirrors include/lrhe.h
+SIGNATURES = {
+    "lrhe_last_error": (ctypes.c_char_p, []),
+    "lrhe_ctx_create": (i32, [ctypes.POINTER(LrheParams), i32, ctypes.POINTER(vp)]),
+    "lrhe_ctx_destroy": (None, [vp]),
+    "lrhe_ctx_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]),
+    "lrhe_galois_element": (i32, [vp, u32, ctypes.POINTER(u32)]),
+    "lrhe_keygen": (i32, [vp, u64, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+    "lrhe_sk_destroy": (None, [vp]),
+    "lrhe_pk_destroy": (None, [vp]),
+    "lrhe_gk_destroy": (None, [vp]),
+    "lrhe_workspace_bytes": (i32, [vp, i32, u32, u32, u32, ctypes.POINTER(u64)]),
+    "lrhe_encrypt_rows": (i32, [vp, vp, vp, u32, u32, u64, u64, vp, vp, sz, vp]),
+    "lrhe_encrypt_cols": (i32, [vp, vp, vp, u32, u32, u64, u64, vp, vp, sz, vp]),
+    "lrhe_model_create": (i32, [vp, vp, vp, u32, u32, vp, ctypes.POINTER(vp)]),
+    "lrhe_model_destroy": (None, [vp]),
+    "lrhe_matmul_fast": (i32, [vp, vp, vp, vp, u32, vp, vp, sz, vp]),
+    "lrhe_matmul_fast_pairs": (i32, [vp, vp, vp, vp, u32, u32, u32, i32, vp, vp, sz, vp]),
+    "lrhe_matmul_standard": (i32, [vp, vp, vp, vp, vp, sz, vp]),
+    "lrhe_decrypt_slots": (i32, [vp, vp, vp, u32, vp, vp, vp]),
+    "lrhe_decrypt_slots_host": (i32, [vp, vp, vp, u32, vp, vp]),
+    "lrhe_host_transform": (i32, [vp, u32, vp, i32]),
+    "lrhe_to_coeff": (i32, [vp, vp, u64, vp, vp]),
+    "lrhe_pk_export": (i32, [vp, vp, vp]),
+    "lrhe_gk_export": (i32, [vp, vp, vp]),
+    "lrhe_sk_export": (i32, [vp, vp, vp]),
+    "lrhe_ntt": (i32, [vp, vp, u64, i32, vp]),
+    "lrhe_prof_enable": (None, [i32]),
+    "lrhe_prof_reset": (None, []),
+    "lrhe_prof_get": (i32, [ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load liblrhe.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} not built: run paper_2204_05496_amd/build.py (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != LRHE_OK:
+        raise LrheError(code, lib().lrhe_last_error().decode())
+
+
+def ptr(x) -> int:
+    """Address of a torch tensor or numpy array (no copies)."""
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data
+    assert x.is_contiguous()
+    return x.data_ptr()

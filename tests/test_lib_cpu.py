@@ -1,0 +1,138 @@
+"""CPU checks of the HIP library: ABI surface, parameter validation and the
+client-side host code (key generation, host transform, exact decryption),
+against the oracle.  No device calls: contexts here are host-only (device -1).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2204_05496_amd as pkg
+    pkg.native.lib()
+    return pkg
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lrhe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lrhe_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_header_symbol(P):
+    names = header_functions()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", P.native.LIBPATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(lrhe_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    # and the binding declares every one of them
+    assert set(names) <= set(P.native.SIGNATURES)
+
+
+def _create(P, n, q, Pm, t, insecure=0):
+    lib = P.native.lib()
+    arr = (ctypes.c_uint32 * len(q))(*q)
+    prm = P.native.LrheParams(n, len(q), arr, Pm, t, insecure)
+    h = ctypes.c_void_p()
+    code = lib.lrhe_ctx_create(ctypes.byref(prm), -1, ctypes.byref(h))
+    if code == 0:
+        lib.lrhe_ctx_destroy(h)
+    return code, lib.lrhe_last_error().decode()
+
+
+def test_parameter_validation(P):
+    p = WL.PARAMS["tiny"]
+    ok = _create(P, p.n, list(p.q), p.P, p.t)
+    assert ok[0] == 0, ok
+    EP = P.native.LRHE_EPARAM
+    assert _create(P, 3000, list(p.q), p.P, p.t)[0] == EP                   # n not a power of two
+    assert _create(P, 512, list(p.q), p.P, p.t)[0] == EP                    # n below the supported range
+    assert _create(P, p.n, [p.q[0], p.q[0] + 2], p.P, p.t)[0] == EP         # composite / not 1 mod 2n
+    assert _create(P, p.n, [p.q[0], p.q[0]], p.P, p.t)[0] == EP             # repeated modulus
+    assert _create(P, p.n, list(p.q), p.P, 65539)[0] == EP                  # t not 1 mod 2n
+    assert _create(P, p.n, [1073754113], p.P, p.t)[0] == EP                 # >= 2^30
+    assert _create(P, p.n, list(WL.PARAMS["tiny3"].q), WL.PARAMS["tiny3"].P, p.t)[0] == EP   # 120 bits > 109
+    assert _create(P, p.n, list(WL.PARAMS["tiny3"].q), WL.PARAMS["tiny3"].P, p.t, insecure=1)[0] == 0
+    assert _create(P, p.n, [], p.P, p.t)[0] == EP                           # L = 0
+
+
+def test_device_calls_refuse_host_only_context(P):
+    p = WL.PARAMS["tiny"]
+    ctx = P.Context.from_params(p, device=-1)
+    keys = ctx.keygen(5, galois=False)
+    lib = P.native.lib()
+    code = lib.lrhe_encrypt_rows(ctx.h, keys.pk, ctypes.c_void_p(8), 1, 10, 1, 0, ctypes.c_void_p(8),
+                                 ctypes.c_void_p(8), 1 << 30, None)
+    assert code == P.native.LRHE_EDEVICE
+
+
+@pytest.mark.parametrize("pname", ["tiny", "tiny3"])
+def test_keygen_matches_oracle(P, pname):
+    p = WL.PARAMS[pname]
+    ctx = P.Context.from_params(p, device=-1)
+    o = O.Oracle(p.n, list(p.q), p.P, p.t)
+    assert ctx.gal == o.gal
+    for seed in (1234, 2**40 + 7):
+        keys = ctx.keygen(seed)
+        ko = o.keygen(seed)
+        assert np.array_equal(ctx.export_sk(keys).astype(np.int64), ko.s)
+        assert np.array_equal(ctx.export_pk(keys).astype(np.uint64), ko.pk)
+        assert np.array_equal(ctx.export_gk(keys).astype(np.uint64), ko.gk)
+
+
+def test_host_transform_is_negacyclic_evaluation(P):
+    """forward(a)[k] = a(psi^(2 brv(k) + 1)) for a primitive 2n-th root psi, and
+    INTT(NTT(a) * NTT(b)) is the negacyclic product (checked against the oracle)."""
+    p = WL.PARAMS["tiny"]
+    ctx = P.Context.from_params(p, device=-1)
+    o = O.Oracle(p.n, list(p.q), p.P, p.t)
+    n, logn = p.n, 12
+    brv = np.array([int(format(k, f"0{logn}b")[::-1], 2) for k in range(n)])
+    rng = np.random.default_rng(3)
+    for mi, m in enumerate(list(p.q) + [p.P, p.t]):
+        X = np.zeros(n, dtype=np.uint32)
+        X[1] = 1
+        R = ctx.host_transform(X, mi).astype(object)
+        psi = int(R[0])   # brv(0) = 0 -> psi^1
+        assert pow(psi, n, m) == m - 1
+        assert all(int(R[k]) == pow(psi, 2 * int(brv[k]) + 1, m) for k in range(0, n, 97))
+        a = rng.integers(0, m, n).astype(np.uint32)
+        b = rng.integers(0, m, n).astype(np.uint32)
+        A, B = ctx.host_transform(a, mi).astype(np.uint64), ctx.host_transform(b, mi).astype(np.uint64)
+        c = ctx.host_transform(((A * B) % m).astype(np.uint32), mi, inverse=True)
+        ref = np.zeros(n, dtype=np.uint64)
+        O.lib().ora_ring_mul(o.ctx, mi if mi <= len(p.q) else -1, O.P(O.u64(a)), O.P(O.u64(b)), O.P(ref))
+        assert np.array_equal(c.astype(np.uint64), ref)
+
+
+@pytest.mark.parametrize("pname", ["tiny", "tiny3"])
+def test_host_decrypt_matches_oracle(P, pname):
+    """Library decryption of oracle ciphertexts (moved to evaluation form with
+    the library's host transform) equals the oracle's exact decryption."""
+    p = WL.PARAMS[pname]
+    ctx = P.Context.from_params(p, device=-1)
+    o = O.Oracle(p.n, list(p.q), p.P, p.t)
+    keys, ko = ctx.keygen(77), o.keygen(77, galois=False)
+    rng = np.random.default_rng(5)
+    z = rng.integers(0, p.t, p.n)
+    ct = o.encrypt_plain(ko, o.encode(z), 9, 3)
+    L = len(p.q)
+    ev = np.zeros((1, 2, L, p.n), dtype=np.uint32)
+    for x in range(2):
+        for j in range(L):
+            ev[0, x, j] = ctx.host_transform(ct[x, j].astype(np.uint32), j)
+    slots, bud = ctx.decrypt_slots_host(keys, ev)
+    zo, bo = o.decrypt_slots(ko, ct)
+    assert np.array_equal(slots[0], zo) and np.array_equal(slots[0], o.centre(z))
+    assert abs(bud[0] - bo) < 1e-6
