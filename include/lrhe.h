@@ -175,6 +175,20 @@ int lrhe_to_coeff(lrhe_ctx* ctx, const uint32_t* in, uint64_t polys, uint32_t* o
  * evaluation form the kernels use, inverse maps back (canonical output). */
 int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* stream);
 
+/* Launch tuning of the fast matmul.  Keys: "le_intt", "le_mac", "le_moddown",
+ * "le_mask" = log2 of the residues each thread holds in that transform kernel
+ * (4, 5 or 6 where the workgroup stays within 1024 threads; default 5), and
+ * "tile" = pairs per tile (default 4096; the workspace size depends on it).
+ * EINVAL for unknown keys or unavailable values. */
+int lrhe_tune_set(lrhe_ctx* ctx, const char* key, int value);
+int lrhe_tune_get(const lrhe_ctx* ctx, const char* key, int* value);
+/* Autotuner: runs lrhe_matmul_fast on the given workload (reps timed runs per
+ * candidate, each kernel timed with HIP events on its stream) and keeps, for
+ * every transform kernel, its fastest residues-per-thread choice in the context.
+ * Uses the kernel timer (lrhe_prof_*), whose totals it resets. */
+int lrhe_autotune_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct, uint32_t rows,
+                       uint32_t* y_out, void* ws, size_t ws_bytes, void* stream, int reps);
+
 /* Opt-in kernel timing: while enabled, every kernel launch of the library is
  * bracketed by HIP events on its own stream.  lrhe_prof_get returns the number
  * of launches and their summed duration (ms) for a kernel name (for example

@@ -239,6 +239,25 @@ class Context:
         N.check(N.lib().lrhe_matmul_standard(self.h, model.handle, N.ptr(fct), N.ptr(out), None, 0, _stream()))
         return out
 
+    def tune_set(self, key: str, value: int):
+        N.check(N.lib().lrhe_tune_set(self.h, key.encode(), value))
+
+    def tune_get(self, key: str) -> int:
+        v = ctypes.c_int()
+        N.check(N.lib().lrhe_tune_get(self.h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def tuning(self) -> dict:
+        return {k: self.tune_get(k) for k in ("le_intt", "le_mac", "le_moddown", "le_mask", "tile")}
+
+    def autotune_fast(self, keys: Keys, model: Model, xct, rows: int, out=None, ws=None, reps: int = 2) -> dict:
+        nout = -(-rows * model.classes // self.n)
+        out = self.empty_ct(nout) if out is None else out
+        ws = self.workspace(N.WS_MATMUL_FAST, rows, model.f, model.classes) if ws is None else ws
+        N.check(N.lib().lrhe_autotune_fast(self.h, keys.gk, model.handle, N.ptr(xct), rows, N.ptr(out), N.ptr(ws),
+                                           ws.numel(), _stream(), reps))
+        return self.tuning()
+
     def to_coeff(self, ct):
         """Canonical coefficient form (device tensor, same shape), for parity checks."""
         out = _torch().empty_like(ct)

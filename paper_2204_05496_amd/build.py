@@ -23,8 +23,20 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _stale(obj: str, src: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(INCLUDE, "lrhe.h"))
+    deps.append(os.path.abspath(__file__))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def _compile(src: str, force: bool = False) -> str:
     obj = os.path.join(BUILD, src + ".o")
+    if not force and not _stale(obj, src):
+        return obj
     cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -32,10 +44,11 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = False) -> str:
+    """Compile (objects whose sources or headers changed, or all with force) and link."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
     tmp = OUT + ".tmp"
     cmd = ["hipcc", "-shared", "-fopenmp", "--offload-arch=gfx950", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,5 +61,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--force" in sys.argv)
     sys.exit(0)

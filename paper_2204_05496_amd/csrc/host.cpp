@@ -15,6 +15,10 @@
 
 using namespace lrhe;
 
+extern "C" void lrhe_prof_enable(int on);
+extern "C" void lrhe_prof_reset(void);
+extern "C" int lrhe_prof_get(const char* kernel, uint64_t* launches, double* total_ms);
+
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
 static int fail(int code, const char* fmt, ...) {
@@ -813,5 +817,83 @@ extern "C" int lrhe_ntt(lrhe_ctx* c, uint32_t* data, uint64_t polys, int inverse
   NEED_DEVICE(c);
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(launch_ntt(c, data, polys * c->L, c->L, 0, inverse != 0, (hipStream_t)stream));
+  return LRHE_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+static bool le_valid(uint32_t logn, int le) {
+  if (le < 4 || le > 6) return false;
+  if ((int)logn - le > 10) return false;   // at most 1024 threads per workgroup
+  if (le == 4 && logn > 14) return false;
+  if (le == 6 && logn < 12) return false;
+  return true;
+}
+
+extern "C" int lrhe_tune_set(lrhe_ctx* c, const char* key, int value) {
+  if (!c || !key) return fail(LRHE_EINVAL, "null argument");
+  const std::string k = key;
+  int* le = nullptr;
+  if (k == "le_intt") le = &c->tune.le_intt;
+  else if (k == "le_mac") le = &c->tune.le_mac;
+  else if (k == "le_moddown") le = &c->tune.le_moddown;
+  else if (k == "le_mask") le = &c->tune.le_mask;
+  else if (k == "tile") {
+    if (value < 1) return fail(LRHE_EINVAL, "tile must be >= 1");
+    c->tune.tile = (uint32_t)value;
+    return LRHE_OK;
+  } else {
+    return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
+  }
+  if (!le_valid(c->logn, value)) return fail(LRHE_EINVAL, "%s = %d not available at n = %u", key, value, c->n);
+  *le = value;
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_tune_get(const lrhe_ctx* c, const char* key, int* value) {
+  if (!c || !key || !value) return fail(LRHE_EINVAL, "null argument");
+  const std::string k = key;
+  if (k == "le_intt") *value = c->tune.le_intt;
+  else if (k == "le_mac") *value = c->tune.le_mac;
+  else if (k == "le_moddown") *value = c->tune.le_moddown;
+  else if (k == "le_mask") *value = c->tune.le_mask;
+  else if (k == "tile") *value = (int)c->tune.tile;
+  else return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
+                                  uint32_t rows, uint32_t* y_out, void* ws, size_t ws_bytes, void* stream, int reps) {
+  if (!c || !gk || !m || !xct || !y_out) return fail(LRHE_EINVAL, "null argument");
+  NEED_DEVICE(c);
+  if (reps < 1) reps = 1;
+  const char* names[4] = {"k_ks_intt", "k_ks_mac", "k_ks_moddown", "k_mask"};
+  int* knobs[4] = {&c->tune.le_intt, &c->tune.le_mac, &c->tune.le_moddown, &c->tune.le_mask};
+  double best_ms[4] = {1e300, 1e300, 1e300, 1e300};
+  int best_le[4] = {c->tune.le_intt, c->tune.le_mac, c->tune.le_moddown, c->tune.le_mask};
+  // every kernel is timed separately with events on its stream; all four knobs
+  // move together and each kernel keeps its own fastest value
+  for (int le = 4; le <= 6; ++le) {
+    if (!le_valid(c->logn, le)) continue;
+    for (int k = 0; k < 4; ++k) *knobs[k] = le;
+    int rc = lrhe_matmul_fast(c, gk, m, xct, rows, y_out, ws, ws_bytes, stream);   // warm-up
+    if (rc != LRHE_OK) return rc;
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    lrhe_prof_reset();
+    lrhe_prof_enable(1);
+    for (int r = 0; r < reps && rc == LRHE_OK; ++r) rc = lrhe_matmul_fast(c, gk, m, xct, rows, y_out, ws, ws_bytes, stream);
+    lrhe_prof_enable(0);
+    if (rc != LRHE_OK) return rc;
+    for (int k = 0; k < 4; ++k) {
+      uint64_t cnt = 0;
+      double ms = 0;
+      lrhe_prof_get(names[k], &cnt, &ms);
+      if (cnt && ms < best_ms[k]) {
+        best_ms[k] = ms;
+        best_le[k] = le;
+      }
+    }
+    lrhe_prof_reset();
+  }
+  for (int k = 0; k < 4; ++k) *knobs[k] = best_le[k];
   return LRHE_OK;
 }

@@ -16,7 +16,53 @@ template <int LOGN>
 using Gm = Geom<LOGN, LOGE>;
 
 // ------------------------------------------------------------------ helpers
+// Read/write view of a device array through a buffer resource held in SGPRs:
+// every access is a scalar base plus a 32-bit per-lane offset (no 64-bit
+// address per lane), and the hardware returns 0 / drops writes outside
+// [0, words).  Word 3 of the resource is the gfx9-family raw-buffer format.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct DBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ DBuf(const uint32_t* p, uint32_t words)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(words * 4u), 0x00020000)) {}
+  __device__ __forceinline__ uint32_t operator[](uint32_t i) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)(i * 4u), 0, 0);
+  }
+  __device__ __forceinline__ u32x4 ld4(uint32_t i) const {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * 4u), 0, 0);
+  }
+  __device__ __forceinline__ void st(uint32_t i, uint32_t v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)(i * 4u), 0, 0);
+  }
+  __device__ __forceinline__ void st4(uint32_t i, u32x4 v) const {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(i * 4u), 0, 0);
+  }
+};
+
+// twiddle table of modulus mi (forward or inverse): per-lane reads through the
+// buffer view, wave-uniform reads as scalar loads through the plain pointer
+struct TwView {
+  DBuf b;
+  const uint32_t* p;
+  __device__ __forceinline__ TwView(const uint32_t* base, int mi, uint32_t n)
+      : b(base + (size_t)mi * n, n), p(base + (size_t)mi * n) {}
+};
+__device__ __forceinline__ uint32_t tw_get(const TwView& tw, uint32_t i, bool uniform) {
+  return uniform ? tw.p[i] : tw.b[i];
+}
+__device__ __forceinline__ TwView twv(const uint32_t* base, int mi, uint32_t n) { return TwView(base, mi, n); }
+
 __device__ __forceinline__ uint32_t dbrv(uint32_t x, int logn) { return __brev(x) >> (32 - logn); }
+
+// Thread id hidden from loop-invariant code motion: inside the digit and pair
+// loops every LDS address, twiddle offset and operand offset derived from it
+// is recomputed (a few ALU ops) instead of being hoisted and kept live in
+// ~100 VGPRs for the whole loop.  An empty register-only asm, no memory access.
+__device__ __forceinline__ int tid_fresh() {
+  uint32_t v = threadIdx.x;
+  asm volatile("" : "+v"(v));
+  return (int)v;
+}
 
 // NTT-domain automorphism: output index k holds the input at auto_perm(k), for
 // sigma_g: a(X) -> a(X^g) with evaluations stored at psi^(2 brv(k) + 1).
@@ -27,8 +73,7 @@ __device__ __forceinline__ uint32_t auto_perm(uint32_t k, uint32_t g, int logn) 
 }
 
 template <class G>
-__device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x, int t) {
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < G::E; ++e) lds[G::pad(G::idx(pfrom, t, e))] = x[e];
@@ -40,11 +85,10 @@ __device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t
 // forward transform: x in pass-0 layout with values < 4q; returns the
 // evaluations in last-pass layout, canonical [0, q)
 template <class G>
-__device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const uint32_t* tw, const Mod& m) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TwView& tw, const Mod& m, int t) {
 #pragma unroll
   for (int p = 0; p < G::NPASS; ++p) {
-    if (p > 0) xchg<G>(lds, p - 1, p, x);
+    if (p > 0) xchg<G>(lds, p - 1, p, x, t);
     fwd_pass<G>(p, t, x, tw, m.q, m.qinv);
   }
 #pragma unroll
@@ -54,59 +98,70 @@ __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const uint32
 // inverse transform: x in last-pass layout with values < 2q; returns canonical
 // coefficients in pass-0 layout
 template <class G>
-__device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const uint32_t* itw, const Mod& m) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const TwView& itw, const Mod& m, int t) {
 #pragma unroll
   for (int p = G::NPASS - 1; p >= 0; --p) {
-    if (p < G::NPASS - 1) xchg<G>(lds, p + 1, p, x);
+    if (p < G::NPASS - 1) xchg<G>(lds, p + 1, p, x, t);
     inv_pass<G>(p, t, x, itw, m.q, m.qinv);
   }
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = red1(mulm(x[e], m.ninv_m, m.q, m.qinv), m.q);
 }
 
-// pass-0 layout: element e of thread t is index e T + t (coalesced)
+// pass-0 layout: element e of thread t is index e T + t (coalesced).  Offsets
+// are 32-bit unsigned and bases wave-uniform, so loads use a scalar base plus a
+// 32-bit vector offset instead of a 64-bit address per lane.
 template <class G>
-__device__ __forceinline__ int idx0(int e) { return e * G::T + threadIdx.x; }
+__device__ __forceinline__ uint32_t idx0(int e, int t) { return (uint32_t)e * G::T + (uint32_t)t; }
 // last-pass layout index
 template <class G>
-__device__ __forceinline__ int idxL(int e) { return G::idx(G::NPASS - 1, threadIdx.x, e); }
+__device__ __forceinline__ uint32_t idxL(int e, int t) { return (uint32_t)G::idx(G::NPASS - 1, t, e); }
+// the same with a fresh thread id per call, for loop bodies (see tid_fresh)
+template <class G>
+__device__ __forceinline__ uint32_t idx0f(int e) { return idx0<G>(e, tid_fresh()); }
+template <class G>
+__device__ __forceinline__ uint32_t idxLf(int e) { return idxL<G>(e, tid_fresh()); }
+
+
 
 template <class G>
-__device__ __forceinline__ void load0(const uint32_t* __restrict__ g, uint32_t* x) {
+__device__ __forceinline__ void load0(const DBuf& g, uint32_t* x, int t) {
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = g[idx0<G>(e)];
+  for (int e = 0; e < G::E; ++e) x[e] = g[idx0<G>(e, t)];
 }
 template <class G>
-__device__ __forceinline__ void store0(uint32_t* __restrict__ g, const uint32_t* x) {
+__device__ __forceinline__ void store0(const DBuf& g, const uint32_t* x, int t) {
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) g[idx0<G>(e)] = x[e];
+  for (int e = 0; e < G::E; ++e) g.st(idx0<G>(e, t), x[e]);
 }
 // last-pass layout: contiguous chunks of 2^r_last residues; vector access when possible
 template <class G>
-__device__ __forceinline__ void loadL(const uint32_t* __restrict__ g, uint32_t* x) {
+__device__ __forceinline__ void loadL(const DBuf& g, uint32_t* x, int t) {
   constexpr int C = 1 << G::r(G::NPASS - 1);
   if constexpr (C % 4 == 0) {
 #pragma unroll
     for (int e = 0; e < G::E; e += 4) {
-      const uint4 v = *reinterpret_cast<const uint4*>(g + idxL<G>(e));
+      const u32x4 v = g.ld4(idxL<G>(e, t));
       x[e] = v.x; x[e + 1] = v.y; x[e + 2] = v.z; x[e + 3] = v.w;
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) x[e] = g[idxL<G>(e)];
+    for (int e = 0; e < G::E; ++e) x[e] = g[idxL<G>(e, t)];
   }
 }
 template <class G>
-__device__ __forceinline__ void storeL(uint32_t* __restrict__ g, const uint32_t* x) {
+__device__ __forceinline__ void storeL(const DBuf& g, const uint32_t* x, int t) {
   constexpr int C = 1 << G::r(G::NPASS - 1);
   if constexpr (C % 4 == 0) {
 #pragma unroll
-    for (int e = 0; e < G::E; e += 4)
-      *reinterpret_cast<uint4*>(g + idxL<G>(e)) = make_uint4(x[e], x[e + 1], x[e + 2], x[e + 3]);
+    for (int e = 0; e < G::E; e += 4) {
+      u32x4 v;
+      v.x = x[e]; v.y = x[e + 1]; v.z = x[e + 2]; v.w = x[e + 3];
+      g.st4(idxL<G>(e, t), v);
+    }
   } else {
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) g[idxL<G>(e)] = x[e];
+    for (int e = 0; e < G::E; ++e) g.st(idxL<G>(e, t), x[e]);
   }
 }
 
@@ -120,19 +175,20 @@ __device__ __forceinline__ uint32_t acc2(uint32_t a, uint32_t v, uint32_t q) {
 template <int LOGN, bool INV>
 __global__ __launch_bounds__(Gm<LOGN>::T) void k_ntt(DevCtx c, uint32_t* data, uint32_t nmod, uint32_t mod0) {
   using G = Gm<LOGN>;
+  const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const size_t p = blockIdx.x;
   const int mi = mod0 + (int)(p % nmod);
-  uint32_t* g = data + p * G::N;
+  const DBuf g(data + p * G::N, G::N);
   uint32_t x[G::E];
   if (!INV) {
-    load0<G>(g, x);
-    ntt_fwd<G>(x, lds, c.tw + (size_t)mi * G::N, c.mod[mi]);
-    storeL<G>(g, x);
+    load0<G>(g, x, t);
+    ntt_fwd<G>(x, lds, twv(c.tw, mi, G::N), c.mod[mi], t);
+    storeL<G>(g, x, t);
   } else {
-    loadL<G>(g, x);
-    ntt_inv<G>(x, lds, c.itw + (size_t)mi * G::N, c.mod[mi]);
-    store0<G>(g, x);
+    loadL<G>(g, x, t);
+    ntt_inv<G>(x, lds, twv(c.itw, mi, G::N), c.mod[mi], t);
+    store0<G>(g, x, t);
   }
 }
 
@@ -154,13 +210,15 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encode(DevCtx c, const int64_t*
                                                         uint32_t rows, uint32_t f, uint32_t K, uint32_t classes,
                                                         uint32_t* __restrict__ m_out, uint32_t* __restrict__ rnd) {
   using G = Gm<LOGN>;
+  const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const size_t ci = blockIdx.x;
-  const uint32_t t = c.t;
+  const uint32_t tm = c.t;
+  const DBuf pos(c.pos_slot, G::N);
   uint32_t x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
-    const uint32_t s = c.pos_slot[idxL<G>(e)];
+    const uint32_t s = pos[idxL<G>(e, t)];
     int64_t v = 0;
     if (mode == SRC_ROWS) {
       const uint64_t i = ci / K, k = ci % K, col = k * G::N + s;
@@ -171,19 +229,20 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encode(DevCtx c, const int64_t*
       const uint64_t j = ci / K, k = ci % K, row = k * G::N + s;
       if (row < f) v = src[row * classes + j];
     }
-    x[e] = mod_t_i64(v, t);
+    x[e] = mod_t_i64(v, tm);
   }
   const int mt = c.L + 1;
-  ntt_inv<G>(x, lds, c.itw + (size_t)mt * G::N, c.mod[mt]);
-  store0<G>(m_out + ci * G::N, x);
+  ntt_inv<G>(x, lds, twv(c.itw, mt, G::N), c.mod[mt], t);
+  store0<G>(DBuf(m_out + ci * G::N, G::N), x, t);
   if (rnd) {
+    const DBuf r(rnd + ci * G::N, G::N);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) {
-      const uint64_t y = (uint64_t)c.qmodt * x[e] + (t - 1) / 2;
-      uint64_t qd = (uint64_t)((double)y / (double)t);
-      if (qd * t > y) --qd;
-      else if ((qd + 1) * t <= y) ++qd;
-      rnd[ci * G::N + idx0<G>(e)] = (uint32_t)qd;
+      const uint64_t y = (uint64_t)c.qmodt * x[e] + (tm - 1) / 2;
+      uint64_t qd = (uint64_t)((double)y / (double)tm);
+      if (qd * tm > y) --qd;
+      else if ((qd + 1) * tm <= y) ++qd;
+      r.st(idx0<G>(e, t), (uint32_t)qd);
     }
   }
 }
@@ -226,36 +285,39 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_
                                                          const uint32_t* __restrict__ rnd,
                                                          uint32_t* __restrict__ ct) {
   using G = Gm<LOGN>;
+  const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const size_t ci = blockIdx.x / c.L;
   const int j = blockIdx.x % c.L;
   const Mod md = c.mod[j];
-  const uint32_t* tw = c.tw + (size_t)j * G::N;
+  const TwView tw = twv(c.tw, j, G::N);
   const int8_t* su = small + ci * 3 * G::N;
+  const DBuf mv(m + ci * G::N, G::N), rv(rnd + ci * G::N, G::N);
   uint32_t U[G::E], x[G::E];
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) U[e] = small_mod(su[idx0<G>(e)], md.q);
-  ntt_fwd<G>(U, lds, tw, md);
+  for (int e = 0; e < G::E; ++e) U[e] = small_mod(su[idx0<G>(e, t)], md.q);
+  ntt_fwd<G>(U, lds, tw, md, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
-    const int k = idx0<G>(e);
-    const uint32_t mm = m[ci * G::N + k];
-    const uint32_t delta = addm(red1(mulm(mm, c.qdivt_m[j], md.q, md.qinv), md.q), rnd[ci * G::N + k], md.q);
+    const uint32_t k = idx0<G>(e, t);
+    const uint32_t delta = addm(red1(mulm(mv[k], c.qdivt_m[j], md.q, md.qinv), md.q), rv[k], md.q);
     x[e] = addm(small_mod(su[G::N + k], md.q), delta, md.q);
   }
-  ntt_fwd<G>(x, lds, tw, md);
+  ntt_fwd<G>(x, lds, tw, md, t);
   uint32_t* out = ct + ci * 2 * c.L * G::N;
-  const uint32_t* pk0 = pk + (size_t)j * G::N;
-  const uint32_t* pk1 = pk + (size_t)(c.L + j) * G::N;
+  const DBuf pk0(pk + (size_t)j * G::N, G::N), pk1(pk + (size_t)(c.L + j) * G::N, G::N);
+  uint32_t v[G::E];
+  loadL<G>(pk0, v, t);
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], pk0[idxL<G>(e)], md.q, md.qinv), md.q), x[e], md.q);
-  storeL<G>(out + (size_t)j * G::N, x);
+  for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], v[e], md.q, md.qinv), md.q), x[e], md.q);
+  storeL<G>(DBuf(out + (size_t)j * G::N, G::N), x, t);
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = small_mod(su[2 * G::N + idx0<G>(e)], md.q);
-  ntt_fwd<G>(x, lds, tw, md);
+  for (int e = 0; e < G::E; ++e) x[e] = small_mod(su[2 * G::N + idx0<G>(e, t)], md.q);
+  ntt_fwd<G>(x, lds, tw, md, t);
+  loadL<G>(pk1, v, t);
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], pk1[idxL<G>(e)], md.q, md.qinv), md.q), x[e], md.q);
-  storeL<G>(out + (size_t)(c.L + j) * G::N, x);
+  for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], v[e], md.q, md.qinv), md.q), x[e], md.q);
+  storeL<G>(DBuf(out + (size_t)(c.L + j) * G::N, G::N), x, t);
 }
 
 // ------------------------------------------------------------------ model encoding
@@ -270,15 +332,17 @@ template <int LOGN>
 __global__ __launch_bounds__(Gm<LOGN>::T) void k_lift_ntt(DevCtx c, const uint32_t* __restrict__ mt,
                                                           uint32_t* __restrict__ out) {
   using G = Gm<LOGN>;
+  const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const size_t pi = blockIdx.x / c.L;
   const int i = blockIdx.x % c.L;
   const Mod md = c.mod[i];
+  const DBuf src(mt + pi * G::N, G::N);
   uint32_t x[G::E];
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = lift_mont(mt[pi * G::N + idx0<G>(e)], c.t, md);
-  ntt_fwd<G>(x, lds, c.tw + (size_t)i * G::N, md);
-  storeL<G>(out + (pi * c.L + i) * G::N, x);
+  for (int e = 0; e < G::E; ++e) x[e] = lift_mont(src[idx0<G>(e, t)], c.t, md);
+  ntt_fwd<G>(x, lds, twv(c.tw, i, G::N), md, t);
+  storeL<G>(DBuf(out + (pi * c.L + i) * G::N, G::N), x, t);
 }
 
 // scalar weights for the standard baseline: wsc[k][j][i] = lift(W[k][j] mod t) R mod q_i
@@ -326,74 +390,95 @@ __global__ __launch_bounds__(256) void k_mac(DevCtx c, const uint32_t* __restric
 }
 
 // key switch, part 1: d_i = INTT(sigma_g(c1))_i, digits in coefficient form
-template <int LOGN>
-__global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_intt(DevCtx c, const uint32_t* __restrict__ cin, uint32_t g,
-                                                         uint32_t* __restrict__ D) {
-  using G = Gm<LOGN>;
+template <int LOGN, int LE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const uint32_t* __restrict__ cin,
+                                                                uint32_t g, uint32_t* __restrict__ D) {
+  using G = Geom<LOGN, LE>;
+  const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const size_t lp = blockIdx.x / c.L;
   const int i = blockIdx.x % c.L;
-  const uint32_t* src = cin + (lp * 2 * c.L + c.L + i) * G::N;
+  const DBuf src(cin + (lp * 2 * c.L + c.L + i) * G::N, G::N);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
-    const int k = idx0<G>(e);
+    const uint32_t k = idx0<G>(e, t);
     lds[G::pad(k)] = src[k];
   }
   __syncthreads();
   uint32_t x[G::E];
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(idxL<G>(e), g, LOGN))];
-  ntt_inv<G>(x, lds, c.itw + (size_t)i * G::N, c.mod[i]);
-  store0<G>(D + (lp * c.L + i) * G::N, x);
+  for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(idxL<G>(e, t), g, LOGN))];
+  ntt_inv<G>(x, lds, twv(c.itw, i, G::N), c.mod[i], t);
+  store0<G>(DBuf(D + (lp * c.L + i) * G::N, G::N), x, t);
 }
 
-// key switch, part 2: for target modulus r, acc_x = sum_i NTT_r(d_i) ksk_{g,i,x,r};
+// key switch, part 2: for target modulus r, acc_x = sum_i NTT_r(d_i) ksk_{g,i,x,r}
+// (for i = r the transform is skipped: NTT_r(d_r) is limb r of sigma_g(c1));
 // r = P additionally returns rho_x = [INTT(acc_x) + (P-1)/2]_P in coefficient form
-template <int LOGN>
-__global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_mac(DevCtx c, const uint32_t* __restrict__ D,
-                                                        const uint32_t* __restrict__ key,
-                                                        uint32_t* __restrict__ ACC) {
-  using G = Gm<LOGN>;
+template <int LOGN, int LE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const uint32_t* __restrict__ cin,
+                                                               const uint32_t* __restrict__ D,
+                                                               const uint32_t* __restrict__ key, uint32_t g,
+                                                               uint32_t* __restrict__ ACC) {
+  using G = Geom<LOGN, LE>;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const int L = c.L;
   const size_t lp = blockIdx.x / (L + 1);
   const int r = blockIdx.x % (L + 1);
   const Mod mr = c.mod[r];
-  const uint32_t* tw = c.tw + (size_t)r * G::N;
-  const uint32_t* kr = key + (size_t)r * L * 2 * G::N;   // [L digits][2][n]
+  const TwView tw = twv(c.tw, r, G::N);
+  const DBuf kr(key + (size_t)r * L * 2 * G::N, (uint32_t)(L * 2 * G::N));   // [L digits][2][n]
+  const DBuf dp(D + lp * L * G::N, (uint32_t)(L * G::N));
   uint32_t ab[G::E], aa[G::E], x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) ab[e] = aa[e] = 0;
   for (int i = 0; i < L; ++i) {
-    load0<G>(D + (lp * L + i) * G::N, x);   // d_i < q_i < 4 q_r: a valid lazy input
-    ntt_fwd<G>(x, lds, tw, mr);
-    const uint32_t* kb = kr + (size_t)(2 * i) * G::N;
-    const uint32_t* ka = kb + G::N;
-    uint32_t vb[G::E], va[G::E];
-    loadL<G>(kb, vb);
-    loadL<G>(ka, va);
+    if (i == r) {
+      // [d_r]_{q_r} in evaluation form is limb r of sigma_g(c1): a permutation of the input
+      const DBuf c1r(cin + (lp * 2 * L + L + r) * G::N, G::N);
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) {
-      ab[e] = acc2(ab[e], mulm(x[e], vb[e], mr.q, mr.qinv), mr.q);
-      aa[e] = acc2(aa[e], mulm(x[e], va[e], mr.q, mr.qinv), mr.q);
+      for (int e = 0; e < G::E; ++e) x[e] = c1r[auto_perm(idxLf<G>(e), g, LOGN)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < G::E; ++e) x[e] = dp[(uint32_t)i * G::N + idx0f<G>(e)];   // d_i < q_i < 4 q_r
+      ntt_fwd<G>(x, lds, tw, mr, tid_fresh());
+    }
+    // keep the key loads below the transform: hoisting them into it costs 64 VGPRs
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t kb = (uint32_t)(2 * i) * G::N, ka = kb + G::N;
+#pragma unroll
+    for (int e = 0; e < G::E; e += 4) {   // last-pass chunks hold >= 4 contiguous residues
+      const uint32_t k = idxLf<G>(e);
+      const u32x4 vb = kr.ld4(kb + k), va = kr.ld4(ka + k);
+      ab[e] = acc2(ab[e], mulm(x[e], vb.x, mr.q, mr.qinv), mr.q);
+      ab[e + 1] = acc2(ab[e + 1], mulm(x[e + 1], vb.y, mr.q, mr.qinv), mr.q);
+      ab[e + 2] = acc2(ab[e + 2], mulm(x[e + 2], vb.z, mr.q, mr.qinv), mr.q);
+      ab[e + 3] = acc2(ab[e + 3], mulm(x[e + 3], vb.w, mr.q, mr.qinv), mr.q);
+      aa[e] = acc2(aa[e], mulm(x[e], va.x, mr.q, mr.qinv), mr.q);
+      aa[e + 1] = acc2(aa[e + 1], mulm(x[e + 1], va.y, mr.q, mr.qinv), mr.q);
+      aa[e + 2] = acc2(aa[e + 2], mulm(x[e + 2], va.z, mr.q, mr.qinv), mr.q);
+      aa[e + 3] = acc2(aa[e + 3], mulm(x[e + 3], va.w, mr.q, mr.qinv), mr.q);
     }
   }
+  const int t = tid_fresh();
   uint32_t* out = ACC + (lp * (L + 1) + r) * 2 * G::N;
+  const DBuf ob(out, G::N), oa(out + G::N, G::N);
   if (r < L) {
 #pragma unroll
     for (int e = 0; e < G::E; ++e) { ab[e] = red1(ab[e], mr.q); aa[e] = red1(aa[e], mr.q); }
-    storeL<G>(out, ab);
-    storeL<G>(out + G::N, aa);
+    storeL<G>(ob, ab, t);
+    storeL<G>(oa, aa, t);
   } else {
     const uint32_t h = (mr.q - 1) / 2;
-    ntt_inv<G>(ab, lds, c.itw + (size_t)r * G::N, mr);
+    const TwView itw = twv(c.itw, r, G::N);
+    ntt_inv<G>(ab, lds, itw, mr, t);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) ab[e] = addm(ab[e], h, mr.q);
-    store0<G>(out, ab);
-    ntt_inv<G>(aa, lds, c.itw + (size_t)r * G::N, mr);
+    store0<G>(ob, ab, t);
+    ntt_inv<G>(aa, lds, itw, mr, t);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) aa[e] = addm(aa[e], h, mr.q);
-    store0<G>(out + G::N, aa);
+    store0<G>(oa, aa, t);
   }
 }
 
@@ -401,68 +486,70 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_mac(DevCtx c, const uint32_t
 // round(acc / P) = (acc - [acc]_P) / P with [acc]_P the centred residue
 // rho_x - h, so out_x = (acc_x - NTT(rho_x - h)) P^-1 mod q_j; then the
 // rotate-and-accumulate c0' = c0 + sigma_g(c0) + out_b, c1' = c1 + out_a
-template <int LOGN>
-__global__ __launch_bounds__(Gm<LOGN>::T) void k_ks_moddown(DevCtx c, const uint32_t* __restrict__ cin,
-                                                            const uint32_t* __restrict__ ACC, uint32_t g,
-                                                            uint32_t* __restrict__ cout) {
-  using G = Gm<LOGN>;
+template <int LOGN, int LE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, const uint32_t* __restrict__ cin,
+                                                                   const uint32_t* __restrict__ ACC, uint32_t g,
+                                                                   uint32_t* __restrict__ cout) {
+  using G = Geom<LOGN, LE>;
+  const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const int L = c.L;
   const size_t lp = blockIdx.x / L;
   const int j = blockIdx.x % L;
   const Mod md = c.mod[j];
-  const uint32_t* tw = c.tw + (size_t)j * G::N;
-  const uint32_t* acc = ACC + (lp * (L + 1) + j) * 2 * G::N;
-  const uint32_t* rho = ACC + (lp * (L + 1) + L) * 2 * G::N;
-  const uint32_t* c0 = cin + (lp * 2 * L + j) * G::N;
-  const uint32_t* c1 = cin + (lp * 2 * L + L + j) * G::N;
-  uint32_t x[G::E], a[G::E];
+  const TwView tw = twv(c.tw, j, G::N);
+  const DBuf acc(ACC + (lp * (L + 1) + j) * 2 * G::N, 2 * G::N);
+  const DBuf rho(ACC + (lp * (L + 1) + L) * 2 * G::N, 2 * G::N);
+  const DBuf c0(cin + (lp * 2 * L + j) * G::N, G::N);
+  const DBuf c1(cin + (lp * 2 * L + L + j) * G::N, G::N);
+  uint32_t x[G::E];
   const uint32_t hq = c.hmod[j], pinv = c.pinv_m[j];
   // b part: rho - h + q_j < P + q_j < 4 q_j is a valid lazy input
-  load0<G>(rho, x);
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] += md.q - hq;
-  ntt_fwd<G>(x, lds, tw, md);
-  loadL<G>(acc, a);
+  for (int e = 0; e < G::E; ++e) x[e] = rho[idx0<G>(e, t)] + md.q - hq;
+  ntt_fwd<G>(x, lds, tw, md, t);
+  uint32_t a[G::E];
+  loadL<G>(acc, a, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
-    const int k = idxL<G>(e);
+    const uint32_t k = idxL<G>(e, t);
     const uint32_t ob = red1(mulm(a[e] + md.q - x[e], pinv, md.q, md.qinv), md.q);
     x[e] = addm(addm(c0[k], c0[auto_perm(k, g, LOGN)], md.q), ob, md.q);
   }
-  storeL<G>(cout + (lp * 2 * L + j) * G::N, x);
+  storeL<G>(DBuf(cout + (lp * 2 * L + j) * G::N, G::N), x, t);
   // a part
-  load0<G>(rho + G::N, x);
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] += md.q - hq;
-  ntt_fwd<G>(x, lds, tw, md);
-  loadL<G>(acc + G::N, a);
+  for (int e = 0; e < G::E; ++e) x[e] = rho[G::N + idx0<G>(e, t)] + md.q - hq;
+  ntt_fwd<G>(x, lds, tw, md, t);
+  const DBuf acca(ACC + (lp * (L + 1) + j) * 2 * G::N + G::N, G::N);
+  loadL<G>(acca, a, t);
   uint32_t cc[G::E];
-  loadL<G>(c1, cc);
+  loadL<G>(c1, cc, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
     const uint32_t oa = red1(mulm(a[e] + md.q - x[e], pinv, md.q, md.qinv), md.q);
     x[e] = addm(cc[e], oa, md.q);
   }
-  storeL<G>(cout + (lp * 2 * L + L + j) * G::N, x);
+  storeL<G>(DBuf(cout + (lp * 2 * L + L + j) * G::N, G::N), x, t);
 }
 
 // bias + one-hot mask of each pair, accumulated per group of G pairs (the
 // compression of Algorithm 1 is a modular sum, so partial sums are exact).
 // mode 0: accumulate into part[group]; mode 1: write each masked pair to
 // out[lp]; mode 2: write each pair with the bias only (no mask) to out[lp].
-template <int LOGN>
-__global__ __launch_bounds__(Gm<LOGN>::T) void k_mask(DevCtx c, const uint32_t* __restrict__ cin,
-                                                      const uint32_t* __restrict__ dbias, uint32_t classes,
-                                                      uint32_t pb, uint32_t B, uint32_t Gp, uint32_t gbase,
-                                                      int mode, uint32_t* __restrict__ out) {
-  using Gg = Gm<LOGN>;
+template <int LOGN, int LE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const uint32_t* __restrict__ cin,
+                                                             const uint32_t* __restrict__ dbias, uint32_t classes,
+                                                             uint32_t pb, uint32_t B, uint32_t Gp, uint32_t gbase,
+                                                             int mode, uint32_t* __restrict__ out) {
+  using Gg = Geom<LOGN, LE>;
   __shared__ uint32_t lds[Gg::LDS_WORDS];
   const int L = c.L;
   const uint32_t grp = blockIdx.x / L;
   const int j = blockIdx.x % L;
   const Mod md = c.mod[j];
-  const uint32_t* tw = c.tw + (size_t)j * Gg::N;
+  const TwView tw = twv(c.tw, j, Gg::N);
+  const DBuf mtab(c.mask_tab, 2 * Gg::N);
   const uint32_t twon_mask = 2 * Gg::N - 1;
   uint32_t a0[Gg::E], a1[Gg::E], x[Gg::E];
 #pragma unroll
@@ -473,47 +560,52 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_mask(DevCtx c, const uint32_t* 
     const uint32_t jc = (uint32_t)(r % classes);
     const uint32_t l = (uint32_t)(r % Gg::N);
     const uint32_t bj = dbias[jc * L + j];
-    const uint32_t* c0 = cin + ((size_t)lp * 2 * L + j) * Gg::N;
-    const uint32_t* c1 = c0 + (size_t)L * Gg::N;
+    const DBuf c0(cin + ((size_t)lp * 2 * L + j) * Gg::N, Gg::N);
+    const DBuf c1(cin + ((size_t)lp * 2 * L + L + j) * Gg::N, Gg::N);
     if (mode == 2) {
       uint32_t* o = out + (size_t)lp * 2 * L * Gg::N;
+      const DBuf o0(o + (size_t)j * Gg::N, Gg::N), o1(o + (size_t)(L + j) * Gg::N, Gg::N);
 #pragma unroll
       for (int e = 0; e < Gg::E; ++e) {
-        const int k = idx0<Gg>(e);
-        o[(size_t)j * Gg::N + k] = addm(c0[k], bj, md.q);
-        o[(size_t)(L + j) * Gg::N + k] = c1[k];
+        const uint32_t k = idx0f<Gg>(e);
+        o0.st(k, addm(c0[k], bj, md.q));
+        o1.st(k, c1[k]);
       }
       continue;
     }
     const uint32_t el = c.slot_exp[l];
 #pragma unroll
-    for (int e = 0; e < Gg::E; ++e) x[e] = lift_mont(c.mask_tab[(el * (uint32_t)idx0<Gg>(e)) & twon_mask], c.t, md);
-    ntt_fwd<Gg>(x, lds, tw, md);
-    uint32_t v0[Gg::E], v1[Gg::E];
-    loadL<Gg>(c0, v0);
-    loadL<Gg>(c1, v1);
+    for (int e = 0; e < Gg::E; ++e) x[e] = lift_mont(mtab[(el * idx0f<Gg>(e)) & twon_mask], c.t, md);
+    ntt_fwd<Gg>(x, lds, tw, md, tid_fresh());
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t w0[Gg::E], w1[Gg::E];
+    loadL<Gg>(c0, w0, tid_fresh());
+    loadL<Gg>(c1, w1, tid_fresh());
 #pragma unroll
     for (int e = 0; e < Gg::E; ++e) {
-      v0[e] = mulm(addm(v0[e], bj, md.q), x[e], md.q, md.qinv);
-      v1[e] = mulm(v1[e], x[e], md.q, md.qinv);
+      const uint32_t v0 = mulm(addm(w0[e], bj, md.q), x[e], md.q, md.qinv);
+      const uint32_t v1 = mulm(w1[e], x[e], md.q, md.qinv);
+      if (mode == 1) {
+        a0[e] = red1(v0, md.q);
+        a1[e] = red1(v1, md.q);
+      } else {
+        a0[e] = acc2(a0[e], v0, md.q);
+        a1[e] = acc2(a1[e], v1, md.q);
+      }
     }
     if (mode == 1) {
       uint32_t* o = out + (size_t)lp * 2 * L * Gg::N;
-#pragma unroll
-      for (int e = 0; e < Gg::E; ++e) { v0[e] = red1(v0[e], md.q); v1[e] = red1(v1[e], md.q); }
-      storeL<Gg>(o + (size_t)j * Gg::N, v0);
-      storeL<Gg>(o + (size_t)(L + j) * Gg::N, v1);
-    } else {
-#pragma unroll
-      for (int e = 0; e < Gg::E; ++e) { a0[e] = acc2(a0[e], v0[e], md.q); a1[e] = acc2(a1[e], v1[e], md.q); }
+      storeL<Gg>(DBuf(o + (size_t)j * Gg::N, Gg::N), a0, tid_fresh());
+      storeL<Gg>(DBuf(o + (size_t)(L + j) * Gg::N, Gg::N), a1, tid_fresh());
     }
   }
+  const int t = tid_fresh();
   if (mode == 0) {
     uint32_t* o = out + (size_t)(gbase + grp) * 2 * L * Gg::N;
 #pragma unroll
     for (int e = 0; e < Gg::E; ++e) { a0[e] = red1(a0[e], md.q); a1[e] = red1(a1[e], md.q); }
-    storeL<Gg>(o + (size_t)j * Gg::N, a0);
-    storeL<Gg>(o + (size_t)(L + j) * Gg::N, a1);
+    storeL<Gg>(DBuf(o + (size_t)j * Gg::N, Gg::N), a0, t);
+    storeL<Gg>(DBuf(o + (size_t)(L + j) * Gg::N, Gg::N), a1, t);
   }
 }
 
@@ -595,6 +687,26 @@ __global__ __launch_bounds__(256) void k_std(DevCtx c, const uint32_t* __restric
     default: return hipErrorInvalidValue;                    \
   }
 
+#define LRHE_DISPATCH_LE(LOGNVAR, LEVAR, ...)                                         \
+  switch ((LOGNVAR) * 8 + (LEVAR)) {                                                   \
+    case 10 * 8 + 4: { constexpr int LN = 10, LE = 4; __VA_ARGS__; } break;            \
+    case 10 * 8 + 5: { constexpr int LN = 10, LE = 5; __VA_ARGS__; } break;            \
+    case 11 * 8 + 4: { constexpr int LN = 11, LE = 4; __VA_ARGS__; } break;            \
+    case 11 * 8 + 5: { constexpr int LN = 11, LE = 5; __VA_ARGS__; } break;            \
+    case 12 * 8 + 4: { constexpr int LN = 12, LE = 4; __VA_ARGS__; } break;            \
+    case 12 * 8 + 5: { constexpr int LN = 12, LE = 5; __VA_ARGS__; } break;            \
+    case 12 * 8 + 6: { constexpr int LN = 12, LE = 6; __VA_ARGS__; } break;            \
+    case 13 * 8 + 4: { constexpr int LN = 13, LE = 4; __VA_ARGS__; } break;            \
+    case 13 * 8 + 5: { constexpr int LN = 13, LE = 5; __VA_ARGS__; } break;            \
+    case 13 * 8 + 6: { constexpr int LN = 13, LE = 6; __VA_ARGS__; } break;            \
+    case 14 * 8 + 4: { constexpr int LN = 14, LE = 4; __VA_ARGS__; } break;            \
+    case 14 * 8 + 5: { constexpr int LN = 14, LE = 5; __VA_ARGS__; } break;            \
+    case 14 * 8 + 6: { constexpr int LN = 14, LE = 6; __VA_ARGS__; } break;            \
+    case 15 * 8 + 5: { constexpr int LN = 15, LE = 5; __VA_ARGS__; } break;            \
+    case 15 * 8 + 6: { constexpr int LN = 15, LE = 6; __VA_ARGS__; } break;            \
+    default: return hipErrorInvalidValue;                                              \
+  }
+
 static inline unsigned blocks_for(uint64_t threads, unsigned bs) { return (unsigned)((threads + bs - 1) / bs); }
 
 hipError_t launch_ntt(const lrhe_ctx* c, uint32_t* data, uint64_t npolys, uint32_t nmod, uint32_t mod0, bool inverse,
@@ -666,7 +778,7 @@ FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes) {
   uint32_t G = 32;
   while (G > 1 && (uint64_t)G * 64 > npairs) G >>= 1;
   w.G = G;
-  uint32_t B = npairs < 4096 ? npairs : 4096;
+  uint32_t B = npairs < c->tune.tile ? npairs : c->tune.tile;
   B = (B + G - 1) / G * G;
   if (B == 0) B = G;
   w.B = B;
@@ -713,14 +825,24 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
     for (int gi = 0; gi < steps; ++gi) {
       const uint32_t g = c->gal[gi];
       const uint32_t* key = gk_d + (size_t)gi * keyw;
-      LRHE_DISPATCH(c->logn, {
-        { ProfScope ps(s, "k_ks_intt");
-          k_ks_intt<LN><<<(unsigned)(Bt * L), Gm<LN>::T, 0, s>>>(c->dc, cur, g, D); }
-        { ProfScope ps(s, "k_ks_mac");
-          k_ks_mac<LN><<<(unsigned)(Bt * (L + 1)), Gm<LN>::T, 0, s>>>(c->dc, D, key, ACC); }
-        { ProfScope ps(s, "k_ks_moddown");
-          k_ks_moddown<LN><<<(unsigned)(Bt * L), Gm<LN>::T, 0, s>>>(c->dc, cur, ACC, g, nxt); }
-      });
+      {
+        ProfScope ps(s, "k_ks_intt");
+        LRHE_DISPATCH_LE(c->logn, c->tune.le_intt, {
+          k_ks_intt<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, g, D);
+        });
+      }
+      {
+        ProfScope ps(s, "k_ks_mac");
+        LRHE_DISPATCH_LE(c->logn, c->tune.le_mac, {
+          k_ks_mac<LN, LE><<<(unsigned)(Bt * (L + 1)), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, key, g, ACC);
+        });
+      }
+      {
+        ProfScope ps(s, "k_ks_moddown");
+        LRHE_DISPATCH_LE(c->logn, c->tune.le_moddown, {
+          k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt);
+        });
+      }
       uint32_t* tmp = cur; cur = nxt; nxt = tmp;
     }
     if (stage >= 2 && stage < 100) {
@@ -728,8 +850,8 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
       continue;
     }
     if (stage == 0 || stage == 100) {   // per-pair export
-      LRHE_DISPATCH(c->logn, {
-        k_mask<LN><<<(unsigned)(((Bt + lay.G - 1) / lay.G) * L), Gm<LN>::T, 0, s>>>(
+      LRHE_DISPATCH_LE(c->logn, c->tune.le_mask, {
+        k_mask<LN, LE><<<(unsigned)(((Bt + lay.G - 1) / lay.G) * L), Geom<LN, LE>::T, 0, s>>>(
             c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G, 0, stage == 0 ? 1 : 2,
             out + (uint64_t)(pb - pair0) * ctw);
       });
@@ -737,9 +859,9 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
     }
     // stage < 0: full Algorithm 1, partial compression per group
     const uint32_t ngt = (Bt + lay.G - 1) / lay.G;
-    LRHE_DISPATCH(c->logn, {
-      ProfScope ps(s, "k_mask");
-      k_mask<LN><<<(unsigned)(ngt * L), Gm<LN>::T, 0, s>>>(c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G,
+    ProfScope ps(s, "k_mask");
+    LRHE_DISPATCH_LE(c->logn, c->tune.le_mask, {
+      k_mask<LN, LE><<<(unsigned)(ngt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G,
                                                              (pb - pair0) / lay.G, 0, part);
     });
   }

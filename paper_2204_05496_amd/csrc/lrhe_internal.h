@@ -40,8 +40,18 @@ struct FastWs {
 
 }  // namespace lrhe
 
+namespace lrhe {
+// Launch choices of the fast-matmul kernels (set by lrhe_tune_set / lrhe_autotune_fast):
+// log2 of the residues per thread of each transform kernel, pairs per tile.
+struct Tune {
+  int le_intt = 5, le_mac = 5, le_moddown = 5, le_mask = 5;
+  uint32_t tile = 4096;
+};
+}  // namespace lrhe
+
 struct lrhe_ctx {
   int device = 0;
+  lrhe::Tune tune;
   uint32_t n = 0, logn = 0, L = 0, ngal = 0, t = 0, P = 0;
   std::vector<uint32_t> q;        // L data primes followed by P
   std::vector<uint32_t> gal;      // Galois elements of the rotate-and-sum

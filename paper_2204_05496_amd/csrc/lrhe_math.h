@@ -24,6 +24,15 @@
 #define LRHE_HD inline
 #endif
 
+// Scheduling fence between butterfly stages in device code: one stage holds
+// E/2 independent butterflies, enough ILP, and the fence stops the scheduler
+// from hoisting later stages' twiddle loads (which costs registers).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LRHE_STAGE_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define LRHE_STAGE_FENCE() ((void)0)
+#endif
+
 namespace lrhe {
 
 struct Mod {
@@ -75,29 +84,34 @@ struct Geom {
   LRHE_HD static constexpr int s0(int p) { return p * LOGE; }
   LRHE_HD static constexpr int r(int p) { return (LOGN - p * LOGE) < LOGE ? (LOGN - p * LOGE) : LOGE; }
   // global index of element e (= u 2^r + c) of thread t in pass p
-  LRHE_HD static int idx(int p, int t, int e) {
+  LRHE_HD static uint32_t idx(int p, int t, int e) {
     const int rr = r(p), sh = s0(p);
-    const int c = e & ((1 << rr) - 1), u = e >> rr;
-    const int sp = u * T + t;
+    const uint32_t c = (uint32_t)e & ((1u << rr) - 1), u = (uint32_t)e >> rr;
+    const uint32_t sp = u * T + (uint32_t)t;
     const int lstride = LOGN - sh - rr;   // log2 of the stride
-    const int h = sp >> lstride, l = sp & ((1 << lstride) - 1);
+    const uint32_t h = sp >> lstride, l = sp & ((1u << lstride) - 1);
     return (h << (LOGN - sh)) + (c << lstride) + l;
   }
   // padded position in the exchange buffer
-  LRHE_HD static int pad(int j) { return j + (j >> LOGE); }
+  LRHE_HD static uint32_t pad(uint32_t j) { return j + (j >> LOGE); }
 };
 
 // One pass of the forward (Cooley-Tukey) transform on the E registers of
 // thread t.  x holds the elements of pass p in Geom::idx order, values in
 // [0, 4q); output in [0, 4q).  tw: psi^brv(k) R mod q, k < n.
-template <class G>
-LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const uint32_t* tw, uint32_t q, uint32_t qinv) {
+// Twiddle access: on the host a plain pointer; in the kernels a view with a
+// per-lane path and a wave-uniform (scalar-load) path.  In the pass that
+// starts at stage 0 the block index h equals u, so its twiddles are uniform.
+LRHE_HD uint32_t tw_get(const uint32_t* tw, uint32_t i, bool) { return tw[i]; }
+
+template <class G, class TW>
+LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint32_t qinv) {
   const int rr = G::r(p), sh = G::s0(p);
   const int lstride = G::LOGN - sh - rr;
   const uint32_t q2 = 2 * q;
 #pragma unroll
   for (int u = 0; u < (G::E >> rr); ++u) {
-    const int h = (u * G::T + t) >> lstride;
+    const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
 #pragma unroll
     for (int tau = 0; tau < rr; ++tau) {
       const int half = 1 << (rr - 1 - tau);
@@ -105,7 +119,7 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const uint32_t* tw, uint32_t q,
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
         const int s = sh + tau;
-        const uint32_t w = tw[(1 << s) + (h << tau) + (c >> (rr - tau))];
+        const uint32_t w = tw_get(tw, (uint32_t)((1 << s) + (h << tau) + (c >> (rr - tau))), sh == 0);
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
         uint32_t X = umin(*a, *a - q2);
@@ -113,6 +127,7 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const uint32_t* tw, uint32_t q,
         *a = X + Tm;
         *b = X + q2 - Tm;
       }
+      LRHE_STAGE_FENCE();
     }
   }
 }
@@ -120,14 +135,14 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const uint32_t* tw, uint32_t q,
 // One pass of the inverse (Gentleman-Sande) transform; passes run in the order
 // NPASS-1 .. 0 and stages inside a pass from the last to the first.  Values in
 // and out in [0, 2q).  itw: psi^-brv(k) R mod q.
-template <class G>
-LRHE_HD void inv_pass(int p, int t, uint32_t* x, const uint32_t* itw, uint32_t q, uint32_t qinv) {
+template <class G, class TW>
+LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint32_t qinv) {
   const int rr = G::r(p), sh = G::s0(p);
   const int lstride = G::LOGN - sh - rr;
   const uint32_t q2 = 2 * q;
 #pragma unroll
   for (int u = 0; u < (G::E >> rr); ++u) {
-    const int h = (u * G::T + t) >> lstride;
+    const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
 #pragma unroll
     for (int tau = rr - 1; tau >= 0; --tau) {
       const int half = 1 << (rr - 1 - tau);
@@ -135,7 +150,7 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const uint32_t* itw, uint32_t q
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
         const int s = sh + tau;
-        const uint32_t w = itw[(1 << s) + (h << tau) + (c >> (rr - tau))];
+        const uint32_t w = tw_get(itw, (uint32_t)((1 << s) + (h << tau) + (c >> (rr - tau))), sh == 0);
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
         uint32_t U = *a + *b;
@@ -144,6 +159,7 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const uint32_t* itw, uint32_t q
         *a = U;
         *b = mulm(V, w, q, qinv);
       }
+      LRHE_STAGE_FENCE();
     }
   }
 }
