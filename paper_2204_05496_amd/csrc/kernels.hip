@@ -72,8 +72,23 @@ __device__ __forceinline__ uint32_t auto_perm(uint32_t k, uint32_t g, int logn) 
   return dbrv((ge - 1) >> 1, logn);
 }
 
-template <class G>
-__device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x, int t) {
+// Exchange between passes.  Single-buffered (DB = false): a barrier before the
+// writes (earlier reads of the buffer must be done) and one after.  Double-
+// buffered (DB = true, two LDS buffers, `par` selects one and flips): the
+// write-after-read barrier is not needed, because consecutive exchanges use
+// different buffers and the barrier of the exchange in between orders them.
+template <class G, bool DB = false>
+__device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x, int t, int* par = nullptr) {
+  if constexpr (DB) {
+    lds += (*par) * G::LDS_WORDS;
+    *par ^= 1;
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) lds[G::pad(G::idx(pfrom, t, e))] = x[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(G::idx(pto, t, e))];
+    return;
+  }
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < G::E; ++e) lds[G::pad(G::idx(pfrom, t, e))] = x[e];
@@ -84,11 +99,12 @@ __device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t
 
 // forward transform: x in pass-0 layout with values < 4q; returns the
 // evaluations in last-pass layout, canonical [0, q)
-template <class G>
-__device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TwView& tw, const Mod& m, int t) {
+template <class G, bool DB = false>
+__device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TwView& tw, const Mod& m, int t,
+                                        int* par = nullptr) {
 #pragma unroll
   for (int p = 0; p < G::NPASS; ++p) {
-    if (p > 0) xchg<G>(lds, p - 1, p, x, t);
+    if (p > 0) xchg<G, DB>(lds, p - 1, p, x, t, par);
     fwd_pass<G>(p, t, x, tw, m.q, m.qinv);
   }
 #pragma unroll
@@ -97,11 +113,12 @@ __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TwView
 
 // inverse transform: x in last-pass layout with values < 2q; returns canonical
 // coefficients in pass-0 layout
-template <class G>
-__device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const TwView& itw, const Mod& m, int t) {
+template <class G, bool DB = false>
+__device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const TwView& itw, const Mod& m, int t,
+                                        int* par = nullptr) {
 #pragma unroll
   for (int p = G::NPASS - 1; p >= 0; --p) {
-    if (p < G::NPASS - 1) xchg<G>(lds, p + 1, p, x, t);
+    if (p < G::NPASS - 1) xchg<G, DB>(lds, p + 1, p, x, t, par);
     inv_pass<G>(p, t, x, itw, m.q, m.qinv);
   }
 #pragma unroll
@@ -421,7 +438,10 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const 
                                                                const uint32_t* __restrict__ key, uint32_t g,
                                                                uint32_t* __restrict__ ACC) {
   using G = Geom<LOGN, LE>;
-  __shared__ uint32_t lds[G::LDS_WORDS];
+  // double-buffered exchange when two buffers fit in the 160 KB of LDS
+  constexpr bool DB = 2 * G::LDS_WORDS * 4 <= 160 * 1024;
+  __shared__ uint32_t lds[(DB ? 2 : 1) * G::LDS_WORDS];
+  int par = 0;
   const int L = c.L;
   const size_t lp = blockIdx.x / (L + 1);
   const int r = blockIdx.x % (L + 1);
@@ -432,6 +452,14 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const 
   uint32_t ab[G::E], aa[G::E], x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) ab[e] = aa[e] = 0;
+  // digits are transformed in order i = 0..L-1 (i != r); the next one is
+  // prefetched into xn while the current transform runs
+  uint32_t xn[G::E];
+  const int first = r == 0 ? 1 : 0;
+  if (first < L) {
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)first * G::N + idx0f<G>(e)];
+  }
   for (int i = 0; i < L; ++i) {
     if (i == r) {
       // [d_r]_{q_r} in evaluation form is limb r of sigma_g(c1): a permutation of the input
@@ -440,8 +468,14 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const 
       for (int e = 0; e < G::E; ++e) x[e] = c1r[auto_perm(idxLf<G>(e), g, LOGN)];
     } else {
 #pragma unroll
-      for (int e = 0; e < G::E; ++e) x[e] = dp[(uint32_t)i * G::N + idx0f<G>(e)];   // d_i < q_i < 4 q_r
-      ntt_fwd<G>(x, lds, tw, mr, tid_fresh());
+      for (int e = 0; e < G::E; ++e) x[e] = xn[e];   // d_i < q_i < 4 q_r: a valid lazy input
+      int nx = i + 1;
+      if (nx == r) ++nx;
+      if (nx < L) {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)nx * G::N + idx0f<G>(e)];
+      }
+      ntt_fwd<G, DB>(x, lds, tw, mr, tid_fresh(), &par);
     }
     // keep the key loads below the transform: hoisting them into it costs 64 VGPRs
     __builtin_amdgcn_sched_barrier(0);
@@ -471,11 +505,11 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const 
   } else {
     const uint32_t h = (mr.q - 1) / 2;
     const TwView itw = twv(c.itw, r, G::N);
-    ntt_inv<G>(ab, lds, itw, mr, t);
+    ntt_inv<G, DB>(ab, lds, itw, mr, t, &par);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) ab[e] = addm(ab[e], h, mr.q);
     store0<G>(ob, ab, t);
-    ntt_inv<G>(aa, lds, itw, mr, t);
+    ntt_inv<G, DB>(aa, lds, itw, mr, t, &par);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) aa[e] = addm(aa[e], h, mr.q);
     store0<G>(oa, aa, t);

@@ -47,7 +47,7 @@ LRHE_HD uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 // x < q 2^32 (or any x with x + (2^32-1) q < 2^64): returns x R^-1 mod q, in [0, 2q)
 // when x < q 2^32, and in [0, x/2^32 + q) otherwise.
 LRHE_HD uint32_t redc(uint64_t x, uint32_t q, uint32_t qinv) {
-  uint32_t m = (uint32_t)x * qinv;
+  const uint32_t m = (uint32_t)x * qinv;
   uint64_t y = x + (uint64_t)m * q;
   return (uint32_t)(y >> 32);
 }
@@ -80,7 +80,10 @@ struct Geom {
   static constexpr int LOGN = LOGN_, LOGE = LOGE_;
   static constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N >> LOGE;
   static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
-  static constexpr int LDS_WORDS = N + (N >> LOGE);   // padded exchange buffer
+  // padded exchange buffer: one pad word per 2^PADSH words keeps every wave's
+  // exchange accesses free of LDS bank conflicts (64 banks, 32 lanes per cycle)
+  static constexpr int PADSH = LOGE == 4 ? 3 : LOGE;
+  static constexpr int LDS_WORDS = N + (N >> PADSH);
   LRHE_HD static constexpr int s0(int p) { return p * LOGE; }
   LRHE_HD static constexpr int r(int p) { return (LOGN - p * LOGE) < LOGE ? (LOGN - p * LOGE) : LOGE; }
   // global index of element e (= u 2^r + c) of thread t in pass p
@@ -93,7 +96,7 @@ struct Geom {
     return (h << (LOGN - sh)) + (c << lstride) + l;
   }
   // padded position in the exchange buffer
-  LRHE_HD static uint32_t pad(uint32_t j) { return j + (j >> LOGE); }
+  LRHE_HD static uint32_t pad(uint32_t j) { return j + (j >> PADSH); }
 };
 
 // One pass of the forward (Cooley-Tukey) transform on the E registers of
