@@ -75,6 +75,111 @@ def cpu_baseline(pname, rows, f, classes, seed):
                       f"encrypt + Algorithm 1 + decrypt, {dt:.1f} s"}
 
 
+def _uneven_inputs(ctx, keys, P, WL, torch, count):
+    reqs = WL.uneven_requests(count=count)
+    models = {}
+    out = []
+    for k, r in enumerate(reqs):
+        if r.f not in models:
+            models[r.f] = ctx.model(r.W, r.b)
+        xct = ctx.encrypt_rows(keys, torch.from_numpy(r.X).cuda(), seed=7000 + k)
+        y = ctx.empty_ct(-(-r.rows * r.classes // ctx.n))
+        out.append((r, xct, models[r.f], y))
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_uneven(ctx, keys, P, WL, O, torch, args):
+    """64 requests (individuals ~ U{1..512}, features ~ U{10000..40000}) in one planned
+    batch: autotuned transform kernels, hipGraph-captured launch sequence; timed replay.
+    Compared with each request run on its own (same kernels, no cross-request tiles)
+    and with the one-ciphertext-at-a-time path (tiles of a single pair), sampled."""
+    log("uneven: encrypt")
+    reqs = _uneven_inputs(ctx, keys, P, WL, torch, args.requests)
+    rows_total = sum(r.rows for r, _, _, _ in reqs)
+    b = P.Batch(ctx, keys, [(xct, r.rows, m, y) for r, xct, m, y in reqs])
+    log("uneven: pairs", b.npairs, "tile", b.tile)
+    tuned = ctx.tuning()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b.capture(side)
+    side.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    # correctness of the replay on a few requests (scores = X W + b mod t)
+    for r, xct, m, y in reqs[:3]:
+        S, _ = ctx.scores_fast(keys, y, r.rows, r.classes)
+        assert np.array_equal(S, O.plain_scores(r.X, r.W, r.b, ctx.t))
+    # each request alone, back to back
+    t0 = time.perf_counter()
+    for r, xct, m, y in reqs:
+        ctx.matmul_fast(keys, m, xct, r.rows, out=y)
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    # one ciphertext at a time (tile = 1 pair), on the first 16 pairs of request 0
+    r0, x0, m0, _ = reqs[0]
+    keep = ctx.tune_get("tile")
+    ctx.tune_set("tile", 1)
+    npairs1 = min(16, r0.rows * r0.classes)
+    ws1 = ctx.workspace(P.native.WS_MATMUL_FAST, npairs1, r0.f, 1)
+    o1 = ctx.empty_ct(npairs1)
+    ctx.matmul_fast_pairs(keys, m0, x0, r0.rows, 0, npairs1, 0, out=o1, ws=ws1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.matmul_fast_pairs(keys, m0, x0, r0.rows, 0, npairs1, 0, out=o1, ws=ws1)
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t0) / npairs1
+    ctx.tune_set("tile", keep)
+    del b
+    torch.cuda.empty_cache()
+    return {"workload": f"uneven_{len(reqs)}req", "requests": len(reqs), "individuals": rows_total,
+            "pairs": sum(r.rows * r.classes for r, _, _, _ in reqs), "tuning": tuned,
+            "graph_s": round(t_graph, 3), "inferences_per_s": round(rows_total / t_graph, 2),
+            "requests_per_s": round(len(reqs) / t_graph, 3),
+            "per_request_alone_s": round(t_alone, 3), "alone_inferences_per_s": round(rows_total / t_alone, 2),
+            "one_ciphertext_at_a_time_pairs_per_s": round(1.0 / t_one, 2),
+            "batched_pairs_per_s": round(sum(r.rows * r.classes for r, _, _, _ in reqs) / t_graph, 1)}
+
+
+def bench_serving(ctx, keys, P, WL, torch, args, ub):
+    """Poisson arrivals of requests sized like the uneven workload at 0.5x and 0.8x
+    the measured batch saturation rate; continuous batching in the native server."""
+    reqs = _uneven_inputs(ctx, keys, P, WL, torch, args.serve_requests)
+    sat = ub["requests_per_s"]
+    res = {}
+    for frac in (0.5, 0.8):
+        qps = frac * sat
+        arrivals = WL.poisson_arrivals(len(reqs), qps, seed=WL.BASE_SEED + int(frac * 10))
+        srv = P.Server(ctx, keys, hbm_budget=args.serve_budget << 30)
+        log(f"serving at {qps:.2f} req/s")
+        ids, refused = [], 0
+        t0 = time.perf_counter()
+        for (r, xct, m, y), ta in zip(reqs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(0.0005)
+            rid = srv.submit(m, xct, r.rows, y)
+            while rid is None:          # admission refused: retry shortly
+                refused += 1
+                time.sleep(0.002)
+                rid = srv.submit(m, xct, r.rows, y)
+            ids.append(rid)
+        srv.drain()
+        wall = time.perf_counter() - t0
+        lat = np.array([srv.poll(i)[1] for i in ids])
+        st = srv.stats()
+        srv.close()
+        rows_total = sum(r.rows for r, _, _, _ in reqs)
+        res[f"qps_{frac}x"] = {"offered_req_per_s": round(qps, 3), "requests": len(reqs),
+                               "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+                               "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+                               "inferences_per_s": round(rows_total / wall, 2), "wall_s": round(wall, 2),
+                               "admission_retries": refused, "ticks": st["ticks"]}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,7 +188,13 @@ def main():
     ap.add_argument("--rows", type=int, default=512)
     ap.add_argument("--features", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip latency / NTT side measurements")
+    ap.add_argument("--cpu-rows", type=int, default=16, help="individuals in the oracle's timed sample")
+    ap.add_argument("--no-extras", action="store_true", help="skip latency / NTT / batching / serving measurements")
+    ap.add_argument("--uneven", type=int, default=1, help="measure the uneven-requests batch (1/0)")
+    ap.add_argument("--serve", type=int, default=1, help="measure the serving loop (1/0)")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-budget", type=int, default=16, help="server partial-sum budget, GiB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -112,6 +223,10 @@ def main():
     y = ctx.empty_ct(nout)
     ws = ctx.workspace(P.native.WS_MATMUL_FAST, rows, wl.f, classes)
     plain = O.plain_scores(wl.X, wl.W, wl.b, p.t)
+    # pick residues-per-thread of the transform kernels by timing them on this workload
+    ctx.encrypt_rows(keys, Xd, seed=3, out=xct, ws=ws_enc)
+    tuned = ctx.autotune_fast(keys, model, xct, rows, out=y, ws=ws)
+    log("tuning", tuned)
 
     def step():
         ctx.encrypt_rows(keys, Xd, seed=3, out=xct, ws=ws_enc)
@@ -232,6 +347,11 @@ def main():
                                   "fwd_avg_ms": round(msf / cf, 3), "inv_avg_ms": round(msi / ci, 3)}
         del buf
 
+    if not args.no_extras and args.uneven:
+        extras["uneven_batch"] = bench_uneven(ctx, keys, P, WL, O, torch, args)
+    if not args.no_extras and args.serve and "uneven_batch" in extras:
+        extras["serving"] = bench_serving(ctx, keys, P, WL, torch, args, extras["uneven_batch"])
+
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -242,6 +362,7 @@ def main():
         "server_inferences_per_s": round(server_rate, 3),
         "noise_budget_bits": round(budget, 1),
         "roofline": roofline,
+        "tuning": tuned,
         "kernels": kern,
         **extras,
         "paper_context": "Threadripper 3960X, SEAL, n=8192, 11 classes: 543 patients in 46.77 s total "
@@ -249,7 +370,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline("n16k", 2, wl.f, classes, WL.BASE_SEED + 7)
+        out["cpu_baseline"] = cpu_baseline("n16k", args.cpu_rows, wl.f, classes, WL.BASE_SEED + 7)
     print(json.dumps(out), flush=True)
 
 

@@ -143,6 +143,47 @@ int lrhe_matmul_fast_pairs(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* m
                            uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* pairs_out,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Many requests (batched and served execution of Algorithm 1) ----
+ * A request is one client's encrypted rows (rows x K ciphertexts from
+ * lrhe_encrypt_rows, K of its model) against one model; its outputs follow the
+ * layout of lrhe_matmul_fast.  Pairs of different requests share tiles; since
+ * every pair is computed independently and the compression is a modular sum,
+ * each request's output ciphertexts are bit-identical to lrhe_matmul_fast on
+ * that request alone. */
+typedef struct {
+  const uint32_t* xct;        /* device, rows x K ciphertexts */
+  uint32_t rows;
+  const lrhe_model* model;
+  uint32_t* y;                /* device, ceil(rows classes / n) ciphertexts */
+} lrhe_request;
+
+typedef struct lrhe_batch lrhe_batch;
+/* Plan a fixed set of requests (descriptors uploaded to the device once). */
+int lrhe_batch_create(lrhe_ctx* ctx, const lrhe_request* reqs, uint32_t nreq, lrhe_batch** out);
+/* Workspace bytes, total pairs, pairs per tile and partial-sum groups of a plan. */
+int lrhe_batch_info(const lrhe_batch* b, uint64_t* ws_bytes, uint32_t* npairs, uint32_t* tile, uint32_t* ngroups);
+/* Run the plan on `stream`; replays the captured graph when one exists for the same ws and keys. */
+int lrhe_batch_run(lrhe_ctx* ctx, const lrhe_gk* gk, lrhe_batch* b, void* ws, size_t ws_bytes, void* stream);
+/* Capture the plan's launch sequence on `stream` (non-default) into a hipGraph for replay. */
+int lrhe_batch_capture(lrhe_ctx* ctx, const lrhe_gk* gk, lrhe_batch* b, void* ws, size_t ws_bytes, void* stream);
+void lrhe_batch_destroy(lrhe_batch* b);
+
+/* Continuous-batching server: the Galois keys stay resident; a worker thread
+ * packs the next `tile` pending pairs of the admitted requests (arrival order)
+ * into each tile, so requests that arrive while others run join the next tile.
+ * hbm_budget bounds the server's partial-sum arena; a request is admitted only
+ * if its partial sums fit (else LRHE_EAGAIN: resubmit later).  Inputs and
+ * outputs are caller-owned device buffers that must stay valid until done. */
+int lrhe_server_create(lrhe_ctx* ctx, const lrhe_gk* gk, size_t hbm_budget, lrhe_server** out);
+int lrhe_server_submit(lrhe_server* s, const lrhe_model* model, const uint32_t* xct, uint32_t rows, uint32_t* y,
+                       uint64_t* req_id);
+/* done = 1 once the request's outputs are written; latency_s = submit -> completion. */
+int lrhe_server_poll(lrhe_server* s, uint64_t req_id, int* done, double* latency_s);
+/* Block until every admitted request is done. */
+int lrhe_server_drain(lrhe_server* s);
+int lrhe_server_stats(lrhe_server* s, uint64_t* ticks, uint64_t* pairs, uint32_t* free_slots, uint32_t* tile);
+void lrhe_server_destroy(lrhe_server* s);
+
 /* Standard baseline: fct = f ciphertexts from lrhe_encrypt_cols;
  * y_out[j] = sum_k fct[k] w_kj + B_j (classes ciphertexts); score (i, j) is
  * slot i of y_out[j]. */

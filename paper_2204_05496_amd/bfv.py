@@ -266,6 +266,92 @@ class Context:
         return out
 
 
+class Batch:
+    """A fixed set of requests (xct, rows, model, y) planned once; run() executes
+    Algorithm 1 for all of them, capture() records the launches in a hipGraph."""
+
+    def __init__(self, ctx: Context, keys: Keys, requests):
+        self.ctx, self.keys = ctx, keys
+        self.requests = list(requests)   # keeps the tensors alive
+        arr = (N.LrheRequest * len(self.requests))()
+        for k, (xct, rows, model, y) in enumerate(self.requests):
+            arr[k] = N.LrheRequest(N.ptr(xct), rows, model.handle, N.ptr(y))
+        h = ctypes.c_void_p()
+        N.check(N.lib().lrhe_batch_create(ctx.h, ctypes.cast(arr, ctypes.c_void_p), len(self.requests),
+                                          ctypes.byref(h)))
+        self.h = h
+        wsb, npairs, tile, ng = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        N.check(N.lib().lrhe_batch_info(h, ctypes.byref(wsb), ctypes.byref(npairs), ctypes.byref(tile),
+                                        ctypes.byref(ng)))
+        self.ws_bytes, self.npairs, self.tile, self.ngroups = wsb.value, npairs.value, tile.value, ng.value
+        torch = _torch()
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=ctx._dev())
+
+    def run(self):
+        N.check(N.lib().lrhe_batch_run(self.ctx.h, self.keys.gk, self.h, N.ptr(self.ws), self.ws.numel(), _stream()))
+
+    def capture(self, stream):
+        """Capture on a (non-default) torch stream; later run() calls on any stream replay the graph."""
+        N.check(N.lib().lrhe_batch_capture(self.ctx.h, self.keys.gk, self.h, N.ptr(self.ws), self.ws.numel(),
+                                           ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().lrhe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server (native worker thread) over resident Galois keys."""
+
+    def __init__(self, ctx: Context, keys: Keys, hbm_budget: int):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        N.check(N.lib().lrhe_server_create(ctx.h, keys.gk, hbm_budget, ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, model: Model, xct, rows: int, y):
+        """Returns the request id, or None when admission is refused (LRHE_EAGAIN)."""
+        rid = ctypes.c_uint64()
+        code = N.lib().lrhe_server_submit(self.h, model.handle, N.ptr(xct), rows, N.ptr(y), ctypes.byref(rid))
+        if code == N.LRHE_EAGAIN:
+            return None
+        N.check(code)
+        self._keep[rid.value] = (xct, y, model)
+        return rid.value
+
+    def poll(self, rid: int):
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        N.check(N.lib().lrhe_server_poll(self.h, rid, ctypes.byref(done), ctypes.byref(lat)))
+        return bool(done.value), lat.value
+
+    def drain(self):
+        N.check(N.lib().lrhe_server_drain(self.h))
+
+    def stats(self) -> dict:
+        t, p, f, b = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        N.check(N.lib().lrhe_server_stats(self.h, ctypes.byref(t), ctypes.byref(p), ctypes.byref(f), ctypes.byref(b)))
+        return {"ticks": t.value, "pairs": p.value, "free_slots": f.value, "tile": b.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().lrhe_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def to_numpy_u32(t) -> np.ndarray:
     """Device int32 tensor of residues -> host uint32 array."""
     return t.cpu().numpy().view(np.uint32)

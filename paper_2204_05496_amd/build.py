@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "liblrhe.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "host.cpp", "prof.cpp"]
+SOURCES = ["kernels.hip", "host.cpp", "prof.cpp", "plan.cpp"]
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
     # packed FP32 instructions stay off in every device compile

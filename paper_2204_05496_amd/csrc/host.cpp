@@ -21,7 +21,8 @@ extern "C" int lrhe_prof_get(const char* kernel, uint64_t* launches, double* tot
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
-static int fail(int code, const char* fmt, ...) {
+namespace lrhe {
+int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -30,6 +31,7 @@ static int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+}  // namespace lrhe
 #define NEED_DEVICE(c) \
   do { if ((c)->device < 0) return fail(LRHE_EDEVICE, "host-only context (device < 0) has no GPU"); } while (0)
 #define HIPCHK(expr)                                                                     \

@@ -7,6 +7,8 @@
 // phases so that each residue makes one HBM round trip per step.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "lrhe_internal.h"
 
 namespace lrhe {
@@ -372,30 +374,29 @@ __global__ void k_scalars(DevCtx c, const int64_t* __restrict__ W, uint64_t coun
 }
 
 // ------------------------------------------------------------------ Algorithm 1
-// chunk products and add_many: out[p][x][j] = sum_k X^[i][k][x][j] W-[jc][k][j]
-__global__ __launch_bounds__(256) void k_mac(DevCtx c, const uint32_t* __restrict__ xct,
-                                             const uint32_t* __restrict__ wpt, uint32_t K, uint32_t classes,
-                                             uint32_t pb, uint32_t B, uint32_t* __restrict__ out) {
+// chunk products and add_many of the tile's pairs:
+// out[lp][x][j] = sum_k xrow[k][x][j] * wcls[k][j]  (evaluation form, Montgomery weights)
+__global__ __launch_bounds__(256) void k_mac(DevCtx c, const PairDesc* __restrict__ pairs, uint32_t B,
+                                             uint32_t* __restrict__ out) {
   const uint32_t n = c.n, L = c.L;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one uint4 each
   const uint64_t per_pair = (uint64_t)2 * L * n / 4;
   const uint64_t lp = gid / per_pair;
   if (lp >= B) return;
-  const uint64_t w4 = gid % per_pair;
-  const uint64_t word = w4 * 4;
+  const uint64_t word = (gid % per_pair) * 4;
   const uint32_t xpoly = (uint32_t)(word / ((uint64_t)L * n));
   const uint32_t j = (uint32_t)((word / n) % L);
   const uint32_t k0 = (uint32_t)(word % n);
-  const uint64_t r = pb + lp, i = r / classes, jc = r % classes;
+  const PairDesc d = pairs[lp];
   const Mod md = c.mod[j];
   uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (uint32_t k = 0; k < K; ++k) {
-    const uint4 xv = *reinterpret_cast<const uint4*>(xct + (((i * K + k) * 2 + xpoly) * L + j) * n + k0);
-    const uint4 wv = *reinterpret_cast<const uint4*>(wpt + ((jc * K + k) * L + j) * n + k0);
+  for (uint32_t k = 0; k < d.K; ++k) {
+    const uint4 xv = *reinterpret_cast<const uint4*>(d.xrow + (((uint64_t)k * 2 + xpoly) * L + j) * n + k0);
+    const uint4 wv = *reinterpret_cast<const uint4*>(d.wcls + ((uint64_t)k * L + j) * n + k0);
     a0 += (uint64_t)xv.x * wv.x; a1 += (uint64_t)xv.y * wv.y;
     a2 += (uint64_t)xv.z * wv.z; a3 += (uint64_t)xv.w * wv.w;
-    if ((k % 8) == 7 || k + 1 == K) {   // at most 8 products below q 2^32 + slack
+    if ((k % 8) == 7 || k + 1 == d.K) {   // at most 8 products: redc input < 8 q^2 + 2^32 q
       s0 = addm(s0, red2(redc(a0, md.q, md.qinv), md.q), md.q);
       s1 = addm(s1, red2(redc(a1, md.q, md.qinv), md.q), md.q);
       s2 = addm(s2, red2(redc(a2, md.q, md.qinv), md.q), md.q);
@@ -567,19 +568,20 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
   storeL<G>(DBuf(cout + (lp * 2 * L + L + j) * G::N, G::N), x, t);
 }
 
-// bias + one-hot mask of each pair, accumulated per group of G pairs (the
-// compression of Algorithm 1 is a modular sum, so partial sums are exact).
-// mode 0: accumulate into part[group]; mode 1: write each masked pair to
-// out[lp]; mode 2: write each pair with the bias only (no mask) to out[lp].
+// bias + one-hot mask of each pair of a group, the group's masked ciphertexts
+// summed into one partial (the compression of Algorithm 1 is a modular sum, so
+// any grouping gives the same output).  mode 0: partial part[group.part]
+// (out = partial base); mode 1: each masked pair to out[lp]; mode 2: each pair
+// with the bias only (no mask) to out[lp].
 template <int LOGN, int LE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const uint32_t* __restrict__ cin,
-                                                             const uint32_t* __restrict__ dbias, uint32_t classes,
-                                                             uint32_t pb, uint32_t B, uint32_t Gp, uint32_t gbase,
-                                                             int mode, uint32_t* __restrict__ out) {
+                                                             const PairDesc* __restrict__ pairs,
+                                                             const GroupDesc* __restrict__ groups, int mode,
+                                                             uint32_t* __restrict__ out) {
   using Gg = Geom<LOGN, LE>;
   __shared__ uint32_t lds[Gg::LDS_WORDS];
   const int L = c.L;
-  const uint32_t grp = blockIdx.x / L;
+  const GroupDesc grp = groups[blockIdx.x / L];
   const int j = blockIdx.x % L;
   const Mod md = c.mod[j];
   const TwView tw = twv(c.tw, j, Gg::N);
@@ -588,12 +590,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const ui
   uint32_t a0[Gg::E], a1[Gg::E], x[Gg::E];
 #pragma unroll
   for (int e = 0; e < Gg::E; ++e) a0[e] = a1[e] = 0;
-  const uint32_t lp0 = grp * Gp, lp1 = min(lp0 + Gp, B);
-  for (uint32_t lp = lp0; lp < lp1; ++lp) {
-    const uint64_t r = (uint64_t)pb + lp;
-    const uint32_t jc = (uint32_t)(r % classes);
-    const uint32_t l = (uint32_t)(r % Gg::N);
-    const uint32_t bj = dbias[jc * L + j];
+  for (uint32_t lp = grp.lp0; lp < grp.lp0 + grp.cnt; ++lp) {
+    const PairDesc d = pairs[lp];
+    const uint32_t bj = d.dbias[j];
     const DBuf c0(cin + ((size_t)lp * 2 * L + j) * Gg::N, Gg::N);
     const DBuf c1(cin + ((size_t)lp * 2 * L + L + j) * Gg::N, Gg::N);
     if (mode == 2) {
@@ -607,7 +606,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const ui
       }
       continue;
     }
-    const uint32_t el = c.slot_exp[l];
+    const uint32_t el = c.slot_exp[d.slot];
 #pragma unroll
     for (int e = 0; e < Gg::E; ++e) x[e] = lift_mont(mtab[(el * idx0f<Gg>(e)) & twon_mask], c.t, md);
     ntt_fwd<Gg>(x, lds, tw, md, tid_fresh());
@@ -635,7 +634,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const ui
   }
   const int t = tid_fresh();
   if (mode == 0) {
-    uint32_t* o = out + (size_t)(gbase + grp) * 2 * L * Gg::N;
+    uint32_t* o = out + (size_t)grp.part * 2 * L * Gg::N;
 #pragma unroll
     for (int e = 0; e < Gg::E; ++e) { a0[e] = red1(a0[e], md.q); a1[e] = red1(a1[e], md.q); }
     storeL<Gg>(DBuf(o + (size_t)j * Gg::N, Gg::N), a0, t);
@@ -643,26 +642,62 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const ui
   }
 }
 
-// compression: y[m] = sum of the partial sums of the groups whose pairs land in output m
-__global__ __launch_bounds__(256) void k_compress(DevCtx c, const uint32_t* __restrict__ part, uint32_t ngroups,
-                                                  uint32_t groups_per_out, uint32_t nout,
-                                                  uint32_t* __restrict__ y) {
+// compression: each output ciphertext is the modular sum of its partials
+__global__ __launch_bounds__(256) void k_compress(DevCtx c, const uint32_t* __restrict__ part,
+                                                  const OutDesc* __restrict__ outs, uint32_t nout) {
   const uint32_t n = c.n, L = c.L;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t ctw = (uint64_t)2 * L * n;
   if (gid >= nout * ctw / 4) return;
   const uint64_t word = gid * 4;
-  const uint32_t m = (uint32_t)(word / ctw);
+  const OutDesc od = outs[word / ctw];
   const uint64_t w = word % ctw;
-  const uint32_t j = (uint32_t)((w / n) % L);
-  const uint32_t q = c.mod[j].q;
+  const uint32_t q = c.mod[(w / n) % L].q;
   uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  const uint32_t g0 = m * groups_per_out, g1 = min(g0 + groups_per_out, ngroups);
-  for (uint32_t g = g0; g < g1; ++g) {
+  for (uint32_t g = od.g0; g < od.g1; ++g) {
     const uint4 v = *reinterpret_cast<const uint4*>(part + g * ctw + w);
     s0 = addm(s0, v.x, q); s1 = addm(s1, v.y, q); s2 = addm(s2, v.z, q); s3 = addm(s3, v.w, q);
   }
-  *reinterpret_cast<uint4*>(y + m * ctw + w) = make_uint4(s0, s1, s2, s3);
+  *reinterpret_cast<uint4*>(od.y + w) = make_uint4(s0, s1, s2, s3);
+}
+
+// descriptors of one request (pairs pair0 .. pair0 + npairs - 1, pair r = i classes + j):
+// tiles of B pairs, groups of G consecutive pairs (G | n and G | B, so a group
+// never straddles a tile or an output ciphertext), output m = r / n
+__global__ __launch_bounds__(256) void k_plan_single(DevCtx c, const uint32_t* xct, const uint32_t* wpt,
+                                                     const uint32_t* dbias, uint32_t K, uint32_t classes,
+                                                     uint32_t pair0, uint32_t npairs, uint32_t B, uint32_t G,
+                                                     uint32_t* y, PairDesc* pairs, GroupDesc* groups,
+                                                     uint32_t ngroups, OutDesc* outs, uint32_t nouts) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n = c.n, L = c.L, ctw = 2 * L * n;
+  if (idx < npairs) {
+    const uint64_t r = (uint64_t)pair0 + idx, i = r / classes, jc = r % classes;
+    PairDesc d;
+    d.xrow = xct + i * K * ctw;
+    d.wcls = wpt + jc * K * L * n;
+    d.dbias = dbias + jc * L;
+    d.K = K;
+    d.slot = (uint32_t)(r % n);
+    pairs[idx] = d;
+  }
+  if (idx < ngroups) {
+    const uint32_t a = idx * G, t = a / B;
+    GroupDesc g;
+    g.lp0 = a - t * B;
+    g.cnt = min(G, npairs - a);
+    g.part = idx;
+    g.pad = 0;
+    groups[idx] = g;
+  }
+  if (idx < nouts) {
+    const uint32_t gpo = (uint32_t)(n / G);
+    OutDesc o;
+    o.y = y + (uint64_t)idx * ctw;
+    o.g0 = idx * gpo;
+    o.g1 = min(o.g0 + gpo, ngroups);
+    outs[idx] = o;
+  }
 }
 
 // ------------------------------------------------------------------ standard baseline
@@ -818,41 +853,42 @@ FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes) {
   w.B = B;
   auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
   const uint64_t ngroups = (npairs + G - 1) / G;
+  const uint64_t nouts = (npairs + n - 1) / n;
+  w.npart = ngroups;
+  w.ndesc_pairs = npairs;
+  w.ndesc_groups = ngroups;
+  w.ndesc_outs = nouts;
   size_t off = 0;
   w.cA = off; off += al(B * ctb);
   w.cB = off; off += al(B * ctb);
   w.D = off; off += al(B * L * n * 4);
   w.ACC = off; off += al(B * (L + 1) * 2 * n * 4);
   w.part = off; off += al(ngroups * ctb);
+  w.desc = off; off += al(npairs * sizeof(PairDesc)) + al(ngroups * sizeof(GroupDesc)) + al(nouts * sizeof(OutDesc));
   w.total = off;
   return w;
 }
 
-hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model* m, const uint32_t* xct,
-                       uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out, void* ws,
-                       const FastWs& lay, hipStream_t s) {
-  (void)rows;
+hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* pairs, uint32_t npairs,
+                       const GroupDesc* groups, const uint32_t* tile_g0, uint32_t B, const OutDesc* outs,
+                       uint32_t nouts, int stage, uint32_t* out, uint32_t* cA, uint32_t* cB, uint32_t* D,
+                       uint32_t* ACC, uint32_t* part, hipStream_t s) {
   const uint64_t n = c->n, L = c->L;
   const uint64_t ctw = 2 * L * n;
-  char* base = (char*)ws;
-  uint32_t* cA = (uint32_t*)(base + lay.cA);
-  uint32_t* cB = (uint32_t*)(base + lay.cB);
-  uint32_t* D = (uint32_t*)(base + lay.D);
-  uint32_t* ACC = (uint32_t*)(base + lay.ACC);
-  uint32_t* part = (uint32_t*)(base + lay.part);
   const size_t keyw = (size_t)(L + 1) * L * 2 * n;
-  const uint32_t pend = pair0 + npairs;
-  for (uint32_t pb = pair0; pb < pend; pb += lay.B) {
-    const uint32_t Bt = min(lay.B, pend - pb);
+  for (uint32_t t = 0, pb = 0; pb < npairs; ++t, pb += B) {
+    const uint32_t Bt = min(B, npairs - pb);
+    const PairDesc* tp = pairs + pb;
+    const GroupDesc* tg = groups + tile_g0[t];
+    const uint32_t ngt = tile_g0[t + 1] - tile_g0[t];
     uint32_t* cur = cA;
     uint32_t* nxt = cB;
     {
       ProfScope ps(s, "k_mac");
-      k_mac<<<blocks_for((uint64_t)Bt * ctw / 4, 256), 256, 0, s>>>(c->dc, xct, m->wpt, m->K, m->classes, pb, Bt,
-                                                                     cur);
+      k_mac<<<blocks_for((uint64_t)Bt * ctw / 4, 256), 256, 0, s>>>(c->dc, tp, Bt, cur);
     }
     if (stage == 1) {
-      (void)hipMemcpyAsync(out + (uint64_t)(pb - pair0) * ctw, cur, (uint64_t)Bt * ctw * 4, hipMemcpyDeviceToDevice, s);
+      (void)hipMemcpyAsync(out + (uint64_t)pb * ctw, cur, (uint64_t)Bt * ctw * 4, hipMemcpyDeviceToDevice, s);
       continue;
     }
     const int steps = (stage >= 2 && stage < 100) ? stage - 2 : (int)c->ngal;
@@ -877,36 +913,48 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
           k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt);
         });
       }
-      uint32_t* tmp = cur; cur = nxt; nxt = tmp;
+      uint32_t* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
     }
     if (stage >= 2 && stage < 100) {
-      (void)hipMemcpyAsync(out + (uint64_t)(pb - pair0) * ctw, cur, (uint64_t)Bt * ctw * 4, hipMemcpyDeviceToDevice, s);
+      (void)hipMemcpyAsync(out + (uint64_t)pb * ctw, cur, (uint64_t)Bt * ctw * 4, hipMemcpyDeviceToDevice, s);
       continue;
     }
-    if (stage == 0 || stage == 100) {   // per-pair export
-      LRHE_DISPATCH_LE(c->logn, c->tune.le_mask, {
-        k_mask<LN, LE><<<(unsigned)(((Bt + lay.G - 1) / lay.G) * L), Geom<LN, LE>::T, 0, s>>>(
-            c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G, 0, stage == 0 ? 1 : 2,
-            out + (uint64_t)(pb - pair0) * ctw);
-      });
-      continue;
-    }
-    // stage < 0: full Algorithm 1, partial compression per group
-    const uint32_t ngt = (Bt + lay.G - 1) / lay.G;
     ProfScope ps(s, "k_mask");
+    const int mode = stage == 0 ? 1 : (stage == 100 ? 2 : 0);
+    uint32_t* dst = mode == 0 ? part : out + (uint64_t)pb * ctw;
     LRHE_DISPATCH_LE(c->logn, c->tune.le_mask, {
-      k_mask<LN, LE><<<(unsigned)(ngt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, m->dbias, m->classes, pb, Bt, lay.G,
-                                                             (pb - pair0) / lay.G, 0, part);
+      k_mask<LN, LE><<<(unsigned)(ngt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, tp, tg, mode, dst);
     });
   }
-  if (stage < 0) {
-    const uint32_t ngroups = (npairs + lay.G - 1) / lay.G;
-    const uint32_t gpo = (uint32_t)(n / lay.G);
-    const uint32_t nout = (uint32_t)((npairs + n - 1) / n);
+  if (stage < 0 && nouts) {
     ProfScope ps(s, "k_compress");
-    k_compress<<<blocks_for((uint64_t)nout * ctw / 4, 256), 256, 0, s>>>(c->dc, part, ngroups, gpo, nout, out);
+    k_compress<<<blocks_for((uint64_t)nouts * ctw / 4, 256), 256, 0, s>>>(c->dc, part, outs, nouts);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model* m, const uint32_t* xct,
+                       uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out, void* ws,
+                       const FastWs& lay, hipStream_t s) {
+  (void)rows;
+  char* base = (char*)ws;
+  auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
+  PairDesc* pairs = (PairDesc*)(base + lay.desc);
+  GroupDesc* groups = (GroupDesc*)((char*)pairs + al(lay.ndesc_pairs * sizeof(PairDesc)));
+  OutDesc* outs = (OutDesc*)((char*)groups + al(lay.ndesc_groups * sizeof(GroupDesc)));
+  const uint32_t ngroups = (uint32_t)lay.ndesc_groups;
+  const uint32_t nouts = stage < 0 ? (uint32_t)lay.ndesc_outs : 0;
+  const uint32_t most = max(npairs, max(ngroups, nouts));
+  k_plan_single<<<blocks_for(most, 256), 256, 0, s>>>(c->dc, xct, m->wpt, m->dbias, m->K, m->classes, pair0, npairs,
+                                                      lay.B, lay.G, out, pairs, groups, ngroups, outs, nouts);
+  std::vector<uint32_t> tile_g0;
+  for (uint32_t pb = 0; pb < npairs; pb += lay.B) tile_g0.push_back(pb / lay.G);
+  tile_g0.push_back(ngroups);
+  return launch_plan(c, gk_d, pairs, npairs, groups, tile_g0.data(), lay.B, outs, nouts, stage, out,
+                     (uint32_t*)(base + lay.cA), (uint32_t*)(base + lay.cB), (uint32_t*)(base + lay.D),
+                     (uint32_t*)(base + lay.ACC), (uint32_t*)(base + lay.part), s);
 }
 
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,

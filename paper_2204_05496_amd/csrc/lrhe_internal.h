@@ -35,7 +35,27 @@ struct DevCtx {
 struct FastWs {
   uint32_t B;                 // pairs per tile
   uint32_t G;                 // pairs per compression group
-  size_t cA, cB, D, ACC, part, total;   // byte offsets, total size
+  size_t cA, cB, D, ACC, part, desc, total;   // byte offsets, total size
+  size_t npart, ndesc_pairs, ndesc_groups, ndesc_outs;
+};
+
+// One (input row, class) pair of Algorithm 1, as the kernels see it.
+struct PairDesc {
+  const uint32_t* xrow;   // the K ciphertexts of the row, [K][2][L][n]
+  const uint32_t* wcls;   // the K plaintexts of the class, [K][L][n] (Montgomery)
+  const uint32_t* dbias;  // Delta(b_class) mod q_i, [L]
+  uint32_t K;             // chunks
+  uint32_t slot;          // one-hot slot l = r mod n of the pair
+};
+// A run of consecutive pairs of one tile that land in one output ciphertext;
+// their masked ciphertexts are summed into partial `part`.
+struct GroupDesc {
+  uint32_t lp0, cnt, part, pad;
+};
+// An output ciphertext: the modular sum of partials [g0, g1).
+struct OutDesc {
+  uint32_t* y;
+  uint32_t g0, g1;
 };
 
 }  // namespace lrhe
@@ -99,6 +119,9 @@ struct lrhe_model {
 };
 
 namespace lrhe {
+// Sets the thread-local message returned by lrhe_last_error; returns code.
+int fail(int code, const char* fmt, ...);
+
 // Records HIP events around a kernel launch on its stream while timing is
 // enabled (lrhe_prof_enable); a no-op otherwise.
 struct ProfScope {
@@ -122,6 +145,13 @@ FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes);
 hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model* m, const uint32_t* xct,
                        uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out, void* ws,
                        const FastWs& lay, hipStream_t s);
+// Descriptor-driven Algorithm 1 over pairs[0, npairs) (device arrays): tiles of B
+// pairs; groups[tile_g0[t] .. tile_g0[t+1]) belong to tile t; stage as in
+// lrhe_matmul_fast_pairs (-1 = full: mask into partials, then compress outs).
+hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* pairs, uint32_t npairs,
+                       const GroupDesc* groups, const uint32_t* tile_g0, uint32_t B, const OutDesc* outs,
+                       uint32_t nouts, int stage, uint32_t* out, uint32_t* cA, uint32_t* cB, uint32_t* D,
+                       uint32_t* ACC, uint32_t* part, hipStream_t s);
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,
                            hipStream_t s);
 }  // namespace lrhe

@@ -26,6 +26,10 @@ class LrheParams(ctypes.Structure):
     _fields_ = [("n", u32), ("L", u32), ("q", ctypes.POINTER(u32)), ("P", u32), ("t", u32), ("allow_insecure", u32)]
 
 
+class LrheRequest(ctypes.Structure):
+    _fields_ = [("xct", ctypes.c_void_p), ("rows", u32), ("model", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
 class LrheError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"lrhe error {code}: {msg}")
@@ -59,6 +63,17 @@ SIGNATURES = {
     "lrhe_gk_export": (i32, [vp, vp, vp]),
     "lrhe_sk_export": (i32, [vp, vp, vp]),
     "lrhe_ntt": (i32, [vp, vp, u64, i32, vp]),
+    "lrhe_batch_create": (i32, [vp, vp, u32, ctypes.POINTER(vp)]),
+    "lrhe_batch_info": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+    "lrhe_batch_run": (i32, [vp, vp, vp, vp, sz, vp]),
+    "lrhe_batch_capture": (i32, [vp, vp, vp, vp, sz, vp]),
+    "lrhe_batch_destroy": (None, [vp]),
+    "lrhe_server_create": (i32, [vp, vp, sz, ctypes.POINTER(vp)]),
+    "lrhe_server_submit": (i32, [vp, vp, vp, u32, vp, ctypes.POINTER(u64)]),
+    "lrhe_server_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+    "lrhe_server_drain": (i32, [vp]),
+    "lrhe_server_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+    "lrhe_server_destroy": (None, [vp]),
     "lrhe_tune_set": (i32, [vp, ctypes.c_char_p, i32]),
     "lrhe_tune_get": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(i32)]),
     "lrhe_autotune_fast": (i32, [vp, vp, vp, vp, u32, vp, vp, sz, vp, i32]),

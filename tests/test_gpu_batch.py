@@ -1,0 +1,169 @@
+"""GPU tests of batched and served execution of Algorithm 1 (many requests).
+
+Each request's output ciphertexts must be bit-identical to the single-request
+path and to the oracle, whether the request runs alone, in a planned batch
+(eager or replayed from a hipGraph), or in the continuous-batching server mixed
+with other requests.  Tolerance: none.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-batch]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P(torch):
+    import paper_2204_05496_amd as pkg
+    pkg.native.lib()
+    return pkg
+
+
+def coeff(ctx, t):
+    from paper_2204_05496_amd import to_numpy_u32
+    return to_numpy_u32(ctx.to_coeff(t)).astype(np.uint64)
+
+
+def make_requests(ctx, keys, specs, seed0, params):
+    """specs: (rows, f, classes); each request has its own model and encryption seed."""
+    reqs = []
+    for k, (rows, f, classes) in enumerate(specs):
+        wl = WL.make(f"r{k}", params, rows, f, classes, 0.02, seed0 + 17 * k)
+        xct = ctx.encrypt_rows(keys, wl.X, seed=seed0 + k)
+        model = ctx.model(wl.W, wl.b)
+        reqs.append((wl, xct, model))
+    return reqs
+
+
+@pytest.fixture(scope="module")
+def tiny_setup(P):
+    p = WL.PARAMS["tiny"]
+    ctx = P.Context.from_params(p, device=0)
+    ctx.tune_set("tile", 64)   # small tiles: requests straddle tiles and groups split there
+    keys = ctx.keygen(1234)
+    specs = [(1, 256, 4), (3, 5000, 16), (7, 9000, 4), (2, 100, 16), (5, 4096, 8)]
+    reqs = make_requests(ctx, keys, specs, 500, "tiny")
+    alone = []
+    for wl, xct, model in reqs:
+        alone.append(coeff(ctx, ctx.matmul_fast(keys, model, xct, wl.rows)))
+    return p, ctx, keys, reqs, alone
+
+
+def test_batch_matches_alone_and_oracle(tiny_setup, P, torch):
+    p, ctx, keys, reqs, alone = tiny_setup
+    ys = [ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n)) for wl, _, _ in reqs]
+    b = P.Batch(ctx, keys, [(xct, wl.rows, model, y) for (wl, xct, model), y in zip(reqs, ys)])
+    say("batch pairs", b.npairs, "tile", b.tile, "groups", b.ngroups)
+    b.run()
+    torch.cuda.synchronize()
+    for k, y in enumerate(ys):
+        assert np.array_equal(coeff(ctx, y), alone[k]), f"request {k}"
+    # oracle on two of them
+    o = O.Oracle(p.n, list(p.q), p.P, p.t)
+    ko = o.keygen(1234)
+    for k in (1, 3):
+        wl = reqs[k][0]
+        xo = o.encrypt_rows(ko, wl.X, seed=500 + k)
+        ref = o.fast_matmul(ko, xo, o.encode_weights(wl.W), wl.b)
+        assert np.array_equal(alone[k], ref), f"request {k} vs oracle"
+
+
+def test_batch_graph_replays(tiny_setup, P, torch):
+    """Replays of the captured graph, with eager library work on the device in
+    between, each equal the eager result."""
+    p, ctx, keys, reqs, alone = tiny_setup
+    ys = [ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n)) for wl, _, _ in reqs]
+    b = P.Batch(ctx, keys, [(xct, wl.rows, model, y) for (wl, xct, model), y in zip(reqs, ys)])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        b.capture(side)
+    side.synchronize()
+    wl0, xct0, m0 = reqs[0]
+    for rep in range(3):
+        for y in ys:
+            y.fill_(0)
+        torch.cuda.synchronize()
+        b.run()
+        other = ctx.matmul_fast(keys, m0, xct0, wl0.rows)   # eager work between replays
+        torch.cuda.synchronize()
+        for k, y in enumerate(ys):
+            assert np.array_equal(coeff(ctx, y), alone[k]), f"replay {rep} request {k}"
+        assert np.array_equal(coeff(ctx, other), alone[0])
+
+
+def test_server_mix_equals_alone(tiny_setup, P, torch):
+    p, ctx, keys, reqs, alone = tiny_setup
+    srv = P.Server(ctx, keys, hbm_budget=2 << 30)
+    ys = []
+    ids = []
+    for k, (wl, xct, model) in enumerate(reqs):
+        y = ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n))
+        ys.append(y)
+        rid = srv.submit(model, xct, wl.rows, y)
+        assert rid is not None
+        ids.append(rid)
+        time.sleep(0.001 * k)
+    srv.drain()
+    for k, rid in enumerate(ids):
+        done, lat = srv.poll(rid)
+        assert done and lat > 0
+        assert np.array_equal(coeff(ctx, ys[k]), alone[k]), f"request {k}"
+    st = srv.stats()
+    assert st["pairs"] == sum(wl.rows * wl.classes for wl, _, _ in reqs)
+    srv.close()
+
+
+def test_server_admission_by_memory(tiny_setup, P, torch):
+    p, ctx, keys, reqs, alone = tiny_setup
+    ctb = 2 * ctx.L * ctx.n * 4
+    wl, xct, model = reqs[4]          # 5 x 8 = 40 pairs
+    srv = P.Server(ctx, keys, hbm_budget=ctb * 8)   # room for one such request's partials
+    y1, y2 = ctx.empty_ct(1), ctx.empty_ct(1)
+    r1 = srv.submit(model, xct, wl.rows, y1)
+    assert r1 is not None
+    r2 = srv.submit(model, xct, wl.rows, y2)      # arrives while r1 holds the arena
+    assert r2 is None
+    srv.drain()
+    r2 = srv.submit(model, xct, wl.rows, y2)
+    assert r2 is not None
+    srv.drain()
+    assert np.array_equal(coeff(ctx, y1), alone[4]) and np.array_equal(coeff(ctx, y2), alone[4])
+    with pytest.raises(P.native.LrheError):        # larger than the whole budget
+        srv.submit(reqs[1][2], reqs[1][1], reqs[1][0].rows * 40, ctx.empty_ct(1))
+    srv.close()
+
+
+def test_uneven_requests_n16k_scores(P, torch):
+    """Requests shaped like the uneven-batching workload (rows and features vary),
+    one launch: bit-identical to each request alone; scores equal X W + b mod t."""
+    p = WL.PARAMS["n16k"]
+    ctx = P.Context.from_params(p, device=0)
+    keys = ctx.keygen(77)
+    specs = [(1, 10000, 16), (5, 40000, 16), (33, 23000, 16), (2, 16384, 16), (17, 31000, 16), (64, 12000, 16)]
+    reqs = make_requests(ctx, keys, specs, 900, "n16k")
+    ys = [ctx.empty_ct(1) for _ in reqs]
+    b = P.Batch(ctx, keys, [(xct, wl.rows, model, y) for (wl, xct, model), y in zip(reqs, ys)])
+    b.run()
+    torch.cuda.synchronize()
+    for k, (wl, xct, model) in enumerate(reqs):
+        alone = ctx.matmul_fast(keys, model, xct, wl.rows)
+        assert torch.equal(alone, ys[k]), f"request {k}"
+        S, budget = ctx.scores_fast(keys, ys[k], wl.rows, wl.classes)
+        assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t)) and budget > 50
