@@ -744,7 +744,7 @@ extern "C" int lrhe_model_create(lrhe_ctx* c, const int64_t* W, const int64_t* b
     }
   }
   hipError_t err = hipMalloc((void**)&m->wpt, (size_t)classes * m->K * L * n * 4);
-  if (err == hipSuccess) err = hipMalloc((void**)&m->wsc, (size_t)f * classes * L * 4);
+  if (err == hipSuccess) err = hipMalloc((void**)&m->wsc, (size_t)f * std_class_pad(classes) * L * 4);
   if (err == hipSuccess) err = hipMalloc((void**)&m->dbias, db.size() * 4);
   if (err == hipSuccess) err = hipMemcpy(m->dbias, db.data(), db.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = launch_model_encode(c, W, f, classes, m->wpt, m->wsc, (hipStream_t)stream);

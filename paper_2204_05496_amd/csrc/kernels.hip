@@ -364,13 +364,16 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_lift_ntt(DevCtx c, const uint32
   storeL<G>(DBuf(out + (pi * c.L + i) * G::N, G::N), x, t);
 }
 
-// scalar weights for the standard baseline: wsc[k][j][i] = lift(W[k][j] mod t) R mod q_i
-__global__ void k_scalars(DevCtx c, const int64_t* __restrict__ W, uint64_t count, uint32_t* __restrict__ wsc) {
+// scalar weights for the standard baseline: wsc[k][i][j] = lift(W[k][j] mod t) R mod q_i,
+// classes padded with zeros to a multiple of 16 (cpad)
+__global__ void k_scalars(DevCtx c, const int64_t* __restrict__ W, uint32_t f, uint32_t classes, uint32_t cpad,
+                          uint32_t* __restrict__ wsc) {
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= count * c.L) return;
-  const uint64_t kj = g / c.L;
-  const int i = (int)(g % c.L);
-  wsc[g] = lift_mont(mod_t_i64(W[kj], c.t), c.t, c.mod[i]);
+  if (g >= (uint64_t)f * c.L * cpad) return;
+  const uint32_t j = (uint32_t)(g % cpad);
+  const uint32_t i = (uint32_t)((g / cpad) % c.L);
+  const uint64_t k = g / ((uint64_t)cpad * c.L);
+  wsc[g] = j < classes ? lift_mont(mod_t_i64(W[k * classes + j], c.t), c.t, c.mod[i]) : 0u;
 }
 
 // ------------------------------------------------------------------ Algorithm 1
@@ -703,44 +706,82 @@ __global__ __launch_bounds__(256) void k_plan_single(DevCtx c, const uint32_t* x
 // ------------------------------------------------------------------ standard baseline
 // y[j][x][i] = sum_k fct[k][x][i] w_kj (+ Delta(b_j) for x = 0); one residue per thread,
 // classes in chunks of 16 held in registers, so every input residue is read once per chunk.
-__global__ __launch_bounds__(256) void k_std(DevCtx c, const uint32_t* __restrict__ fct,
-                                             const uint32_t* __restrict__ wsc, const uint32_t* __restrict__ dbias,
-                                             uint32_t f, uint32_t classes, uint32_t* __restrict__ y) {
+// Standard baseline (one ciphertext per feature, individuals in the slots):
+// y[j] = sum_k fct[k] * w[k][j] + Delta(b_j), coefficient-wise over every word
+// of the ciphertexts (a scalar product commutes with the transform).
+// Block: 64 consecutive words x STD_WAVES waves; wave v sums its slice of the
+// features for all 16 classes of a class chunk with 64-bit multiply-adds, the
+// slices meet in LDS.  Every fct word is read once; the weights of one feature
+// and limb are 16 consecutive words, wave-uniform (scalar loads).
+// Accumulator bound: products < q^2 < 2^60; STD_UNROLL = 8 of them on top of a
+// folded value < 2^61 + 2^32 stay below 2^64.  fold(x) = hi(x) (2^32 mod q) +
+// lo(x) is congruent to x and below 2^61 + 2^32.
+constexpr int STD_WAVES = 8, STD_UNROLL = 8, STD_CJ = 16;
+static_assert(STD_CJ == 16, "std_class_pad pads to 16 classes");
+__device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r1) {
+  return (uint64_t)(uint32_t)(x >> 32) * r1 + (uint32_t)x;
+}
+__global__ __launch_bounds__(64 * STD_WAVES) void k_std(DevCtx c, const uint32_t* __restrict__ fct,
+                                                        const uint32_t* __restrict__ wst,
+                                                        const uint32_t* __restrict__ dbias, uint32_t f,
+                                                        uint32_t classes, uint32_t* __restrict__ y) {
+  __shared__ uint32_t part[STD_WAVES][STD_CJ][64];
   const uint32_t n = c.n, L = c.L;
+  const uint32_t cpad = (classes + STD_CJ - 1) / STD_CJ * STD_CJ;
   const uint64_t ctw = (uint64_t)2 * L * n;
-  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;   // word within a ciphertext
-  if (w >= ctw) return;
-  const uint32_t xpoly = (uint32_t)(w / ((uint64_t)L * n));
-  const uint32_t i = (uint32_t)((w / n) % L);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t w0 = (uint64_t)blockIdx.x * 64;            // 64 | n: one limb, one polynomial per block
+  const uint64_t w = w0 + lane;
+  const uint32_t i = (uint32_t)((w0 / n) % L);
+  const uint32_t xpoly = (uint32_t)(w0 / ((uint64_t)L * n));
   const Mod md = c.mod[i];
-  for (uint32_t j0 = 0; j0 < classes; j0 += 16) {
-    const uint32_t nj = min(16u, classes - j0);
-    uint64_t acc[16];
-    uint32_t s[16];
+  const uint32_t r1 = red1(redc(md.r2, md.q, md.qinv), md.q);   // 2^32 mod q
+  const uint32_t k0 = (uint32_t)((uint64_t)f * wave / STD_WAVES);
+  const uint32_t k1 = (uint32_t)((uint64_t)f * (wave + 1) / STD_WAVES);
+  for (uint32_t j0 = 0; j0 < cpad; j0 += STD_CJ) {
+    uint64_t acc[STD_CJ];
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) { acc[jj] = 0; s[jj] = 0; }
-    for (uint32_t k = 0; k < f; ++k) {
-      const uint32_t v = fct[(uint64_t)k * ctw + w];
-      const uint32_t* wk = wsc + ((uint64_t)k * classes + j0) * L + i;
+    for (int j = 0; j < STD_CJ; ++j) acc[j] = 0;
+    uint32_t k = k0;
+    for (; k + STD_UNROLL <= k1; k += STD_UNROLL) {
+      uint32_t v[STD_UNROLL];
+      const uint32_t* src = fct + (uint64_t)k * ctw + w;
 #pragma unroll
-      for (int jj = 0; jj < 16; ++jj)
-        if (jj < (int)nj) acc[jj] += (uint64_t)v * wk[(size_t)jj * L];
-      if ((k % 8) == 7 || k + 1 == f) {
+      for (int u = 0; u < STD_UNROLL; ++u) v[u] = __builtin_nontemporal_load(src + (uint64_t)u * ctw);
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
-          s[jj] = addm(s[jj], red2(redc(acc[jj], md.q, md.qinv), md.q), md.q);
-          acc[jj] = 0;
-        }
+      for (int u = 0; u < STD_UNROLL; ++u) {
+        const uint32_t* wk = wst + ((uint64_t)(k + u) * L + i) * cpad + j0;
+#pragma unroll
+        for (int j = 0; j < STD_CJ; ++j) acc[j] += (uint64_t)v[u] * wk[j];
       }
+#pragma unroll
+      for (int j = 0; j < STD_CJ; ++j) acc[j] = fold32(acc[j], r1);
+    }
+    for (; k < k1; ++k) {
+      const uint32_t v = __builtin_nontemporal_load(fct + (uint64_t)k * ctw + w);
+      const uint32_t* wk = wst + ((uint64_t)k * L + i) * cpad + j0;
+#pragma unroll
+      for (int j = 0; j < STD_CJ; ++j) acc[j] = fold32(acc[j] + (uint64_t)v * wk[j], r1);
     }
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      if (jj < (int)nj) {
-        uint32_t v = s[jj];
-        if (xpoly == 0) v = addm(v, dbias[(j0 + jj) * L + i], md.q);
-        y[(uint64_t)(j0 + jj) * ctw + w] = v;
+    for (int j = 0; j < STD_CJ; ++j) {
+      // two folds: < 2^59.2 < q 2^32, so redc lands in [0, 2q); weights carry R
+      part[wave][j][lane] = red1(redc(fold32(fold32(acc[j], r1), r1), md.q, md.qinv), md.q);
+    }
+    __syncthreads();
+    for (uint32_t o = threadIdx.x; o < STD_CJ * 64; o += 64 * STD_WAVES) {
+      const uint32_t j = o >> 6, l = o & 63;
+      uint32_t sum = 0;
+#pragma unroll
+      for (int v = 0; v < STD_WAVES; ++v) sum = addm(sum, part[v][j][l], md.q);
+      const uint32_t cls = j0 + j;
+      if (cls < classes) {
+        if (xpoly == 0) sum = addm(sum, dbias[(uint64_t)cls * L + i], md.q);
+        y[(uint64_t)cls * ctw + w0 + l] = sum;
       }
     }
+    __syncthreads();
   }
 }
 
@@ -831,8 +872,8 @@ hipError_t launch_model_encode(const lrhe_ctx* c, const int64_t* W, uint32_t f, 
     k_encode<LN><<<(unsigned)npt, Gm<LN>::T, 0, s>>>(c->dc, W, SRC_WT, 0, f, K, classes, mt, nullptr);
     k_lift_ntt<LN><<<(unsigned)(npt * c->L), Gm<LN>::T, 0, s>>>(c->dc, mt, wpt);
   });
-  const uint64_t cnt = (uint64_t)f * classes;
-  k_scalars<<<blocks_for(cnt * c->L, 256), 256, 0, s>>>(c->dc, W, cnt, wsc);
+  const uint32_t cpad = std_class_pad(classes);
+  k_scalars<<<blocks_for((uint64_t)f * c->L * cpad, 256), 256, 0, s>>>(c->dc, W, f, classes, cpad, wsc);
   err = hipGetLastError();
   (void)hipFreeAsync(mt, s);
   return err;
@@ -961,7 +1002,7 @@ hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_
                            hipStream_t s) {
   const uint64_t ctw = (uint64_t)2 * c->L * c->n;
   ProfScope ps(s, "k_std");
-  k_std<<<blocks_for(ctw, 256), 256, 0, s>>>(c->dc, fct, m->wsc, m->dbias, m->f, m->classes, y_out);
+  k_std<<<(unsigned)(ctw / 64), 64 * STD_WAVES, 0, s>>>(c->dc, fct, m->wsc, m->dbias, m->f, m->classes, y_out);
   return hipGetLastError();
 }
 

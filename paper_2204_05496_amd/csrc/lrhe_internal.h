@@ -32,6 +32,9 @@ struct DevCtx {
 };
 
 // Offsets into the fast-matmul workspace for a tile of B pairs.
+// classes of the standard baseline's scalar-weight table, padded to its class chunk
+inline uint32_t std_class_pad(uint32_t classes) { return (classes + 15) / 16 * 16; }
+
 struct FastWs {
   uint32_t B;                 // pairs per tile
   uint32_t G;                 // pairs per compression group
@@ -114,7 +117,7 @@ struct lrhe_gk {
 struct lrhe_model {
   uint32_t f = 0, classes = 0, K = 0;
   uint32_t* wpt = nullptr;      // [classes][K][L][n] evaluation form, Montgomery
-  uint32_t* wsc = nullptr;      // [f][classes][L] centred scalar weights, Montgomery
+  uint32_t* wsc = nullptr;      // [f][L][std_class_pad(classes)] centred scalar weights, Montgomery
   uint32_t* dbias = nullptr;    // [classes][L] Delta(b_j) mod q_i
 };
 
