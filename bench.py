@@ -46,12 +46,16 @@ def prof_get(lib, name):
 
 def ks_mac_modmuls(n, L, pairs):
     """Algorithmic modular multiplications of one k_ks_mac launch over `pairs`
-    ciphertexts: per target modulus r (L + 1 of them) L forward transforms
-    (n/2 log2 n butterflies, one modmul each) and 2 L n inner-product products;
-    the special-prime item adds two inverse transforms and their n^-1 scaling."""
+    ciphertexts.  For a data modulus r: the L - 1 digits d_i (i != r) go through a
+    forward transform mod r (n/2 log2 n butterflies, one modmul each; d_r mod q_r
+    is already limb r of sigma_g(c1)) and the 2 L n inner-product products.  For
+    the special prime: L forward transforms, 2 L n products, and two inverse
+    transforms with their n^-1 scaling."""
     logn = int(np.log2(n))
-    per_r = L * (n // 2) * logn + 2 * L * n
-    return pairs * ((L + 1) * per_r + 2 * ((n // 2) * logn + n))
+    ntt = (n // 2) * logn
+    per_q = (L - 1) * ntt + 2 * L * n
+    per_p = L * ntt + 2 * L * n + 2 * (ntt + n)
+    return pairs * (L * per_q + per_p)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ks_mac_traffic_batch_512x40000x16.txt")
@@ -67,16 +71,17 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def counted_traffic(le_mac):
+def counted_traffic(le_mac, mac_mode):
     """HBM bytes per k_ks_mac launch from the committed FETCH_SIZE / WRITE_SIZE counter
     summary, already scaled by the copy-kernel calibration; None when the kernel
-    sources or its residues-per-thread choice differ from those the counters saw."""
+    sources or its launch variant differ from those the counters saw."""
     try:
         kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_source_sha256") != kernel_source_digest() or int(kv.get("le_mac", -1)) != le_mac:
+    if (kv.get("kernel_source_sha256") != kernel_source_digest() or int(kv.get("le_mac", -1)) != le_mac
+            or int(kv.get("mac_mode", -1)) != mac_mode):
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
 
@@ -311,7 +316,7 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_ks_mac", "achieved": round(achieved, 3), "peak": round(MODMUL_PEAK_T, 3),
                 "unit": "Tmodmul/s", "frac": round(achieved / MODMUL_PEAK_T, 4),
-                "traffic": counted_traffic(tuned["le_mac"]) if rows * classes >= 4096 else None,
+                "traffic": counted_traffic(tuned["large"]["le_mac"], tuned["large"]["mac_mode"]) if rows * classes >= 4096 else None,
                 "avg_launch_ms": round(avg_ms, 4), "modmul_per_launch": per_launch}
 
     # server-only rate (Algorithm 1 on resident ciphertexts)
@@ -351,6 +356,8 @@ def main():
 
         s1 = one_fast()
         assert np.array_equal(s1, O.plain_scores(w1.X, w1.W, w1.b, p.t))
+        # the latency-bound tile class (16 pairs) keeps its own launch choices
+        ctx.autotune_fast(keys, m1, x1, 1, out=y1, ws=ws1)
         fast_ms = timeit(one_fast, 5)
         fast_srv_ms = timeit(lambda: ctx.matmul_fast(keys, m1, x1, 1, out=y1, ws=ws1), 5)
         fct = ctx.empty_ct(w1.f)
@@ -405,7 +412,7 @@ def main():
         "server_inferences_per_s": round(server_rate, 3),
         "noise_budget_bits": round(budget, 1),
         "roofline": roofline,
-        "tuning": tuned,
+        "tuning": ctx.tuning(),
         "kernels": kern,
         **extras,
         "paper_context": "Threadripper 3960X, SEAL, n=8192, 11 classes: 543 patients in 46.77 s total "

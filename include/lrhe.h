@@ -218,14 +218,25 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
 
 /* Launch tuning of the fast matmul.  Keys: "le_intt", "le_mac", "le_moddown",
  * "le_mask" = log2 of the residues each thread holds in that transform kernel
- * (4, 5 or 6 where the workgroup stays within 1024 threads; default 5), and
+ * (4, 5 or 6 where the workgroup stays within 1024 threads; default 5),
+ * "mac_mode" = variant of the key-switch inner-product kernel: 0 (default):
+ * one LDS exchange buffer and two workgroups per CU, the workgroups of a pair
+ * on one XCD; 1: as 0 with the twiddles of the next butterfly stage loaded
+ * ahead; 2: double-buffered exchange with twiddles ahead; 3: double-buffered
+ * exchange with the next digit loaded ahead.  These five keys exist in two
+ * classes, for tiles of fewer than "small_below" pairs (default 1024; such
+ * launches are latency-bound) and for larger tiles: "small.<key>" and
+ * "large.<key>" address one class, a bare key sets both and reads the large
+ * class.  Defaults: large 5/5/5/5 and mac_mode 0, small 5/5/5/5 and mac_mode 3.
  * "tile" = pairs per tile (default 4096; the workspace size depends on it).
- * EINVAL for unknown keys or unavailable values. */
+ * No choice changes any result bit.  EINVAL for unknown keys or unavailable
+ * values. */
 int lrhe_tune_set(lrhe_ctx* ctx, const char* key, int value);
 int lrhe_tune_get(const lrhe_ctx* ctx, const char* key, int* value);
 /* Autotuner: runs lrhe_matmul_fast on the given workload (reps timed runs per
- * candidate, each kernel timed with HIP events on its stream) and keeps, for
- * every transform kernel, its fastest residues-per-thread choice in the context.
+ * candidate, each kernel timed with HIP events on its stream) and keeps, in
+ * the tuning class of this job's tiles, every transform kernel's fastest
+ * residues-per-thread choice, searched jointly with "mac_mode" for k_ks_mac.
  * Uses the kernel timer (lrhe_prof_*), whose totals it resets. */
 int lrhe_autotune_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct, uint32_t rows,
                        uint32_t* y_out, void* ws, size_t ws_bytes, void* stream, int reps);

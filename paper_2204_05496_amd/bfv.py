@@ -248,7 +248,10 @@ class Context:
         return v.value
 
     def tuning(self) -> dict:
-        return {k: self.tune_get(k) for k in ("le_intt", "le_mac", "le_moddown", "le_mask", "tile")}
+        names = ("le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode")
+        return {"large": {k: self.tune_get("large." + k) for k in names},
+                "small": {k: self.tune_get("small." + k) for k in names},
+                "tile": self.tune_get("tile"), "small_below": self.tune_get("small_below")}
 
     def autotune_fast(self, keys: Keys, model: Model, xct, rows: int, out=None, ws=None, reps: int = 2) -> dict:
         nout = -(-rows * model.classes // self.n)

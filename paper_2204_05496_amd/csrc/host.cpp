@@ -831,35 +831,56 @@ static bool le_valid(uint32_t logn, int le) {
   return true;
 }
 
+// key = [small. | large.] name; without a prefix, set applies to both classes
+// and get reads the large-tile class
+static lrhe::Knobs* knob_class(lrhe_ctx* c, std::string& k, bool* both) {
+  *both = false;
+  if (k.rfind("small.", 0) == 0) { k = k.substr(6); return &c->tune.small; }
+  if (k.rfind("large.", 0) == 0) { k = k.substr(6); return &c->tune.large; }
+  *both = true;
+  return &c->tune.large;
+}
+static int* knob_field(lrhe::Knobs* kn, const std::string& k) {
+  if (k == "le_intt") return &kn->le_intt;
+  if (k == "le_mac") return &kn->le_mac;
+  if (k == "le_moddown") return &kn->le_moddown;
+  if (k == "le_mask") return &kn->le_mask;
+  if (k == "mac_mode") return &kn->mac_mode;
+  return nullptr;
+}
+
 extern "C" int lrhe_tune_set(lrhe_ctx* c, const char* key, int value) {
   if (!c || !key) return fail(LRHE_EINVAL, "null argument");
-  const std::string k = key;
-  int* le = nullptr;
-  if (k == "le_intt") le = &c->tune.le_intt;
-  else if (k == "le_mac") le = &c->tune.le_mac;
-  else if (k == "le_moddown") le = &c->tune.le_moddown;
-  else if (k == "le_mask") le = &c->tune.le_mask;
-  else if (k == "tile") {
-    if (value < 1) return fail(LRHE_EINVAL, "tile must be >= 1");
-    c->tune.tile = (uint32_t)value;
+  std::string k = key;
+  if (k == "tile" || k == "small_below") {
+    if (value < 1) return fail(LRHE_EINVAL, "%s must be >= 1", key);
+    (k == "tile" ? c->tune.tile : c->tune.small_below) = (uint32_t)value;
     return LRHE_OK;
-  } else {
-    return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
   }
-  if (!le_valid(c->logn, value)) return fail(LRHE_EINVAL, "%s = %d not available at n = %u", key, value, c->n);
-  *le = value;
+  bool both = false;
+  lrhe::Knobs* kn = knob_class(c, k, &both);
+  int* f = knob_field(kn, k);
+  if (!f) return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
+  if (k == "mac_mode") {
+    if (value < 0 || value >= LRHE_MAC_NMODES) return fail(LRHE_EINVAL, "mac_mode must be in [0, %d)", LRHE_MAC_NMODES);
+  } else if (!le_valid(c->logn, value)) {
+    return fail(LRHE_EINVAL, "%s = %d not available at n = %u", key, value, c->n);
+  }
+  *f = value;
+  if (both) *knob_field(&c->tune.small, k) = value;
   return LRHE_OK;
 }
 
 extern "C" int lrhe_tune_get(const lrhe_ctx* c, const char* key, int* value) {
   if (!c || !key || !value) return fail(LRHE_EINVAL, "null argument");
-  const std::string k = key;
-  if (k == "le_intt") *value = c->tune.le_intt;
-  else if (k == "le_mac") *value = c->tune.le_mac;
-  else if (k == "le_moddown") *value = c->tune.le_moddown;
-  else if (k == "le_mask") *value = c->tune.le_mask;
-  else if (k == "tile") *value = (int)c->tune.tile;
-  else return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
+  std::string k = key;
+  if (k == "tile") { *value = (int)c->tune.tile; return LRHE_OK; }
+  if (k == "small_below") { *value = (int)c->tune.small_below; return LRHE_OK; }
+  bool both = false;
+  lrhe::Knobs* kn = knob_class(const_cast<lrhe_ctx*>(c), k, &both);
+  const int* f = knob_field(kn, k);
+  if (!f) return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
+  *value = *f;
   return LRHE_OK;
 }
 
@@ -868,34 +889,58 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   if (!c || !gk || !m || !xct || !y_out) return fail(LRHE_EINVAL, "null argument");
   NEED_DEVICE(c);
   if (reps < 1) reps = 1;
-  const char* names[4] = {"k_ks_intt", "k_ks_mac", "k_ks_moddown", "k_mask"};
-  int* knobs[4] = {&c->tune.le_intt, &c->tune.le_mac, &c->tune.le_moddown, &c->tune.le_mask};
-  double best_ms[4] = {1e300, 1e300, 1e300, 1e300};
-  int best_le[4] = {c->tune.le_intt, c->tune.le_mac, c->tune.le_moddown, c->tune.le_mask};
-  // every kernel is timed separately with events on its stream; all four knobs
-  // move together and each kernel keeps its own fastest value
-  for (int le = 4; le <= 6; ++le) {
-    if (!le_valid(c->logn, le)) continue;
-    for (int k = 0; k < 4; ++k) *knobs[k] = le;
+  // the class of this job's tiles is the one tuned
+  const uint64_t npairs = (uint64_t)rows * m->classes;
+  lrhe::Knobs& K = c->tune.knobs(std::min<uint64_t>(npairs, c->tune.tile));
+  const char* names[4] = {"k_ks_intt", "k_ks_moddown", "k_mask", "k_ks_mac"};
+  int* knobs[3] = {&K.le_intt, &K.le_moddown, &K.le_mask};
+  double best_ms[3] = {1e300, 1e300, 1e300}, best_mac = 1e300;
+  int best_le[3] = {K.le_intt, K.le_moddown, K.le_mask}, best_mac_le = K.le_mac, best_mode = K.mac_mode;
+  auto timed = [&](double* ms_out, int nk) -> int {
     int rc = lrhe_matmul_fast(c, gk, m, xct, rows, y_out, ws, ws_bytes, stream);   // warm-up
     if (rc != LRHE_OK) return rc;
-    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(LRHE_EDEVICE, "autotune: stream");
     lrhe_prof_reset();
     lrhe_prof_enable(1);
     for (int r = 0; r < reps && rc == LRHE_OK; ++r) rc = lrhe_matmul_fast(c, gk, m, xct, rows, y_out, ws, ws_bytes, stream);
     lrhe_prof_enable(0);
-    if (rc != LRHE_OK) return rc;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < nk; ++k) {
       uint64_t cnt = 0;
+      ms_out[k] = 1e300;
       double ms = 0;
       lrhe_prof_get(names[k], &cnt, &ms);
-      if (cnt && ms < best_ms[k]) {
-        best_ms[k] = ms;
-        best_le[k] = le;
-      }
+      if (cnt) ms_out[k] = ms;
     }
     lrhe_prof_reset();
+    return rc;
+  };
+  // every kernel is timed separately with events on its stream; each keeps its
+  // own fastest residues-per-thread choice; k_ks_mac is searched jointly over
+  // residues per thread and variant
+  for (int le = 4; le <= 6; ++le) {
+    if (!le_valid(c->logn, le)) continue;
+    K.le_intt = K.le_moddown = K.le_mask = K.le_mac = le;
+    for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
+      K.mac_mode = mode;
+      double ms[4];
+      const int rc = timed(ms, 4);
+      if (rc != LRHE_OK) return rc;
+      if (mode == 0) {
+        for (int k = 0; k < 3; ++k)
+          if (ms[k] < best_ms[k]) {
+            best_ms[k] = ms[k];
+            best_le[k] = le;
+          }
+      }
+      if (ms[3] < best_mac) {
+        best_mac = ms[3];
+        best_mac_le = le;
+        best_mode = mode;
+      }
+    }
   }
-  for (int k = 0; k < 4; ++k) *knobs[k] = best_le[k];
+  for (int k = 0; k < 3; ++k) *knobs[k] = best_le[k];
+  K.le_mac = best_mac_le;
+  K.mac_mode = best_mode;
   return LRHE_OK;
 }

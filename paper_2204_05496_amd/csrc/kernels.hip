@@ -101,13 +101,13 @@ __device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t
 
 // forward transform: x in pass-0 layout with values < 4q; returns the
 // evaluations in last-pass layout, canonical [0, q)
-template <class G, bool DB = false>
+template <class G, bool DB = false, bool PF = false>
 __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TwView& tw, const Mod& m, int t,
                                         int* par = nullptr) {
 #pragma unroll
   for (int p = 0; p < G::NPASS; ++p) {
     if (p > 0) xchg<G, DB>(lds, p - 1, p, x, t, par);
-    fwd_pass<G>(p, t, x, tw, m.q, m.qinv);
+    fwd_pass<G, PF>(p, t, x, tw, m.q, m.qinv);
   }
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = red2(x[e], m.q);
@@ -115,13 +115,13 @@ __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TwView
 
 // inverse transform: x in last-pass layout with values < 2q; returns canonical
 // coefficients in pass-0 layout
-template <class G, bool DB = false>
+template <class G, bool DB = false, bool PF = false>
 __device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const TwView& itw, const Mod& m, int t,
                                         int* par = nullptr) {
 #pragma unroll
   for (int p = G::NPASS - 1; p >= 0; --p) {
     if (p < G::NPASS - 1) xchg<G, DB>(lds, p + 1, p, x, t, par);
-    inv_pass<G>(p, t, x, itw, m.q, m.qinv);
+    inv_pass<G, PF>(p, t, x, itw, m.q, m.qinv);
   }
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = red1(mulm(x[e], m.ninv_m, m.q, m.qinv), m.q);
@@ -181,6 +181,24 @@ __device__ __forceinline__ void storeL(const DBuf& g, const uint32_t* x, int t) 
   } else {
 #pragma unroll
     for (int e = 0; e < G::E; ++e) g.st(idxL<G>(e, t), x[e]);
+  }
+}
+
+// four residues e .. e + 3 (e a multiple of 4) of the last-pass layout at
+// base + index: one vector load when the last pass keeps chunks of at least 4
+// contiguous residues, else four loads (a last pass of 1 stage keeps pairs)
+template <class G>
+__device__ __forceinline__ u32x4 ld4L(const DBuf& g, uint32_t base, int e) {
+  constexpr int C = 1 << G::r(G::NPASS - 1);
+  if constexpr (C % 4 == 0) {
+    return g.ld4(base + idxLf<G>(e));
+  } else {
+    u32x4 v;
+    v.x = g[base + idxLf<G>(e)];
+    v.y = g[base + idxLf<G>(e + 1)];
+    v.z = g[base + idxLf<G>(e + 2)];
+    v.w = g[base + idxLf<G>(e + 3)];
+    return v;
   }
 }
 
@@ -436,19 +454,36 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // key switch, part 2: for target modulus r, acc_x = sum_i NTT_r(d_i) ksk_{g,i,x,r}
 // (for i = r the transform is skipped: NTT_r(d_r) is limb r of sigma_g(c1));
 // r = P additionally returns rho_x = [INTT(acc_x) + (P-1)/2]_P in coefficient form
-template <int LOGN, int LE>
-__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const uint32_t* __restrict__ cin,
-                                                               const uint32_t* __restrict__ D,
-                                                               const uint32_t* __restrict__ key, uint32_t g,
-                                                               uint32_t* __restrict__ ACC) {
+// Variants (MODE bits; none changes a result bit): 1 = double-buffered LDS
+// exchange (one barrier per exchange) where two buffers fit in the 160 KB of
+// LDS; 2 = the next digit is loaded during the current transform; 4 = the
+// twiddles of the next butterfly stage are loaded during the current one;
+// 8 = a register cap that lets two workgroups share a CU (only useful
+// single-buffered).
+template <int LOGN, int LE, int MODE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
+    DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const uint32_t* __restrict__ key,
+    uint32_t g, uint32_t* __restrict__ ACC) {
   using G = Geom<LOGN, LE>;
-  // double-buffered exchange when two buffers fit in the 160 KB of LDS
-  constexpr bool DB = 2 * G::LDS_WORDS * 4 <= 160 * 1024;
+  constexpr bool DB = (MODE & 1) && 2 * G::LDS_WORDS * 4 <= 160 * 1024;
+  constexpr bool DP = (MODE & 2) != 0;   // digit prefetch
+  constexpr bool PF = (MODE & 4) != 0;   // twiddle prefetch
   __shared__ uint32_t lds[(DB ? 2 : 1) * G::LDS_WORDS];
   int par = 0;
   const int L = c.L;
-  const size_t lp = blockIdx.x / (L + 1);
-  const int r = blockIdx.x % (L + 1);
+  // consecutive workgroups go to the 8 XCDs in turn.  MODE 64: the L + 1
+  // workgroups of a pair run on one XCD, one after the other, so the pair's
+  // digits are fetched into that XCD's L2 once.
+  uint32_t li = blockIdx.x;
+  if constexpr ((MODE & 64) != 0) {
+    if (gridDim.x % 8 == 0) li = (li % 8) * (gridDim.x / 8) + li / 8;
+  }
+  const size_t lp = li / (L + 1);
+  // the special-prime item (r = L) carries more work than the others, so its
+  // XCD is rotated per pair (MODE 16: between two XCDs, MODE 32: over all)
+  int r = (int)(li % (L + 1));
+  if constexpr ((MODE & 16) != 0) r = (r + ((L + 1) / 2) * (int)(lp & 1)) % (L + 1);
+  if constexpr ((MODE & 32) != 0) r = (r + (int)(lp % (L + 1))) % (L + 1);
   const Mod mr = c.mod[r];
   const TwView tw = twv(c.tw, r, G::N);
   const DBuf kr(key + (size_t)r * L * 2 * G::N, (uint32_t)(L * 2 * G::N));   // [L digits][2][n]
@@ -458,36 +493,43 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const 
   for (int e = 0; e < G::E; ++e) ab[e] = aa[e] = 0;
   // digits are transformed in order i = 0..L-1 (i != r); the next one is
   // prefetched into xn while the current transform runs
-  uint32_t xn[G::E];
-  const int first = r == 0 ? 1 : 0;
-  if (first < L) {
+  [[maybe_unused]] uint32_t xn[DP ? G::E : 1];
+  if constexpr (DP) {
+    const int first = r == 0 ? 1 : 0;
+    if (first < L) {
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)first * G::N + idx0f<G>(e)];
+      for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)first * G::N + idx0f<G>(e)];
+    }
   }
   for (int i = 0; i < L; ++i) {
+    const uint32_t kb = (uint32_t)(2 * i) * G::N, ka = kb + G::N;
     if (i == r) {
       // [d_r]_{q_r} in evaluation form is limb r of sigma_g(c1): a permutation of the input
       const DBuf c1r(cin + (lp * 2 * L + L + r) * G::N, G::N);
 #pragma unroll
       for (int e = 0; e < G::E; ++e) x[e] = c1r[auto_perm(idxLf<G>(e), g, LOGN)];
     } else {
+      // d_i < q_i < 4 q_r: a valid lazy input
+      if constexpr (DP) {
 #pragma unroll
-      for (int e = 0; e < G::E; ++e) x[e] = xn[e];   // d_i < q_i < 4 q_r: a valid lazy input
-      int nx = i + 1;
-      if (nx == r) ++nx;
-      if (nx < L) {
+        for (int e = 0; e < G::E; ++e) x[e] = xn[e];
+        int nx = i + 1;
+        if (nx == r) ++nx;
+        if (nx < L) {
 #pragma unroll
-        for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)nx * G::N + idx0f<G>(e)];
+          for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)nx * G::N + idx0f<G>(e)];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) x[e] = dp[(uint32_t)i * G::N + idx0f<G>(e)];
       }
-      ntt_fwd<G, DB>(x, lds, tw, mr, tid_fresh(), &par);
+      ntt_fwd<G, DB, PF>(x, lds, tw, mr, tid_fresh(), &par);
     }
     // keep the key loads below the transform: hoisting them into it costs 64 VGPRs
     __builtin_amdgcn_sched_barrier(0);
-    const uint32_t kb = (uint32_t)(2 * i) * G::N, ka = kb + G::N;
 #pragma unroll
-    for (int e = 0; e < G::E; e += 4) {   // last-pass chunks hold >= 4 contiguous residues
-      const uint32_t k = idxLf<G>(e);
-      const u32x4 vb = kr.ld4(kb + k), va = kr.ld4(ka + k);
+    for (int e = 0; e < G::E; e += 4) {
+      const u32x4 vb = ld4L<G>(kr, kb, e), va = ld4L<G>(kr, ka, e);
       ab[e] = acc2(ab[e], mulm(x[e], vb.x, mr.q, mr.qinv), mr.q);
       ab[e + 1] = acc2(ab[e + 1], mulm(x[e + 1], vb.y, mr.q, mr.qinv), mr.q);
       ab[e + 2] = acc2(ab[e + 2], mulm(x[e + 2], vb.z, mr.q, mr.qinv), mr.q);
@@ -509,11 +551,11 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_mac(DevCtx c, const 
   } else {
     const uint32_t h = (mr.q - 1) / 2;
     const TwView itw = twv(c.itw, r, G::N);
-    ntt_inv<G, DB>(ab, lds, itw, mr, t, &par);
+    ntt_inv<G, DB, PF>(ab, lds, itw, mr, t, &par);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) ab[e] = addm(ab[e], h, mr.q);
     store0<G>(ob, ab, t);
-    ntt_inv<G, DB>(aa, lds, itw, mr, t, &par);
+    ntt_inv<G, DB, PF>(aa, lds, itw, mr, t, &par);
 #pragma unroll
     for (int e = 0; e < G::E; ++e) aa[e] = addm(aa[e], h, mr.q);
     store0<G>(oa, aa, t);
@@ -532,8 +574,12 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
   const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const int L = c.L;
-  const size_t lp = blockIdx.x / L;
-  const int j = blockIdx.x % L;
+  // the L workgroups of a pair run on one XCD one after the other (consecutive
+  // workgroups go to the 8 XCDs in turn), so rho is fetched into its L2 once
+  uint32_t li = blockIdx.x;
+  if (gridDim.x % 8 == 0) li = (li % 8) * (gridDim.x / 8) + li / 8;
+  const size_t lp = li / L;
+  const int j = (int)(li % L);
   const Mod md = c.mod[j];
   const TwView tw = twv(c.tw, j, G::N);
   const DBuf acc(ACC + (lp * (L + 1) + j) * 2 * G::N, 2 * G::N);
@@ -786,6 +832,16 @@ __global__ __launch_bounds__(64 * STD_WAVES) void k_std(DevCtx c, const uint32_t
 }
 
 // ------------------------------------------------------------------ launchers
+// k_ks_mac variants selectable through the "mac_mode" tuning key (index -> MODE bits)
+#ifndef LRHE_MAC_MODES
+#define LRHE_MAC_MODE_CASE(IDX, LN, LE, MODE) \
+  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, key, g, ACC); break;
+#define LRHE_MAC_MODES(LN, LE)                                                           \
+  LRHE_MAC_MODE_CASE(0, LN, LE, 104) /* one buffer, 2 workgroups/CU, pair per XCD, rotated */ \
+  LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
+  LRHE_MAC_MODE_CASE(2, LN, LE, 37)  /* double buffer, twiddle prefetch, rotated */           \
+  LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */
+#endif
 #define LRHE_DISPATCH(LOGNVAR, ...)                          \
   switch (LOGNVAR) {                                         \
     case 10: { constexpr int LN = 10; __VA_ARGS__; } break; \
@@ -919,6 +975,7 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
   const size_t keyw = (size_t)(L + 1) * L * 2 * n;
   for (uint32_t t = 0, pb = 0; pb < npairs; ++t, pb += B) {
     const uint32_t Bt = min(B, npairs - pb);
+    const Knobs& kn = c->tune.knobs(Bt);
     const PairDesc* tp = pairs + pb;
     const GroupDesc* tg = groups + tile_g0[t];
     const uint32_t ngt = tile_g0[t + 1] - tile_g0[t];
@@ -938,19 +995,23 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
       const uint32_t* key = gk_d + (size_t)gi * keyw;
       {
         ProfScope ps(s, "k_ks_intt");
-        LRHE_DISPATCH_LE(c->logn, c->tune.le_intt, {
+        LRHE_DISPATCH_LE(c->logn, kn.le_intt, {
           k_ks_intt<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, g, D);
         });
       }
       {
         ProfScope ps(s, "k_ks_mac");
-        LRHE_DISPATCH_LE(c->logn, c->tune.le_mac, {
-          k_ks_mac<LN, LE><<<(unsigned)(Bt * (L + 1)), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, key, g, ACC);
+        LRHE_DISPATCH_LE(c->logn, kn.le_mac, {
+          const unsigned grid = (unsigned)(Bt * (L + 1));
+          switch (kn.mac_mode) {
+            LRHE_MAC_MODES(LN, LE)
+            default: return hipErrorInvalidValue;
+          }
         });
       }
       {
         ProfScope ps(s, "k_ks_moddown");
-        LRHE_DISPATCH_LE(c->logn, c->tune.le_moddown, {
+        LRHE_DISPATCH_LE(c->logn, kn.le_moddown, {
           k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt);
         });
       }
@@ -965,7 +1026,7 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
     ProfScope ps(s, "k_mask");
     const int mode = stage == 0 ? 1 : (stage == 100 ? 2 : 0);
     uint32_t* dst = mode == 0 ? part : out + (uint64_t)pb * ctw;
-    LRHE_DISPATCH_LE(c->logn, c->tune.le_mask, {
+    LRHE_DISPATCH_LE(c->logn, kn.le_mask, {
       k_mask<LN, LE><<<(unsigned)(ngt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, tp, tg, mode, dst);
     });
   }

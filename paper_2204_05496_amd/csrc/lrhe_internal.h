@@ -66,9 +66,23 @@ struct OutDesc {
 namespace lrhe {
 // Launch choices of the fast-matmul kernels (set by lrhe_tune_set / lrhe_autotune_fast):
 // log2 of the residues per thread of each transform kernel, pairs per tile.
-struct Tune {
+#ifndef LRHE_MAC_NMODES
+#define LRHE_MAC_NMODES 4   // k_ks_mac variants behind the "mac_mode" tuning key
+#endif
+// Launch choices of the transform kernels (none changes a result bit).
+struct Knobs {
   int le_intt = 5, le_mac = 5, le_moddown = 5, le_mask = 5;
+  int mac_mode = 0;   // variant of k_ks_mac, 0 .. LRHE_MAC_NMODES - 1
+};
+// Tiles below small_below pairs (latency-bound: fewer workgroups than the chip
+// holds) and larger tiles (throughput-bound) keep separate choices.
+struct Tune {
+  Knobs large;
+  Knobs small{5, 5, 5, 5, 3};
   uint32_t tile = 4096;
+  uint32_t small_below = 1024;
+  const Knobs& knobs(uint64_t tile_pairs) const { return tile_pairs < small_below ? small : large; }
+  Knobs& knobs(uint64_t tile_pairs) { return tile_pairs < small_below ? small : large; }
 };
 }  // namespace lrhe
 

@@ -99,30 +99,48 @@ struct Geom {
   LRHE_HD static uint32_t pad(uint32_t j) { return j + (j >> PADSH); }
 };
 
-// One pass of the forward (Cooley-Tukey) transform on the E registers of
-// thread t.  x holds the elements of pass p in Geom::idx order, values in
-// [0, 4q); output in [0, 4q).  tw: psi^brv(k) R mod q, k < n.
 // Twiddle access: on the host a plain pointer; in the kernels a view with a
 // per-lane path and a wave-uniform (scalar-load) path.  In the pass that
 // starts at stage 0 the block index h equals u, so its twiddles are uniform.
 LRHE_HD uint32_t tw_get(const uint32_t* tw, uint32_t i, bool) { return tw[i]; }
 
+// Twiddles of one (unit u, stage tau) step of a pass: the 2^tau distinct values
+// w[j] = tw[2^(s0 + tau) + h 2^tau + j], h the unit's block index.
 template <class G, class TW>
-LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint32_t qinv) {
+LRHE_HD void stage_tw(int p, int t, int u, int tau, const TW& tw, uint32_t* w) {
   const int rr = G::r(p), sh = G::s0(p);
   const int lstride = G::LOGN - sh - rr;
-  const uint32_t q2 = 2 * q;
+  const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
 #pragma unroll
-  for (int u = 0; u < (G::E >> rr); ++u) {
-    const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
+  for (int j = 0; j < (1 << tau); ++j) w[j] = tw_get(tw, (uint32_t)((1 << (sh + tau)) + (h << tau) + j), sh == 0);
+}
+
+// One pass of the forward (Cooley-Tukey) transform on the E registers of
+// thread t.  x holds the elements of pass p in Geom::idx order, values in
+// [0, 4q); output in [0, 4q).  tw: psi^brv(k) R mod q, k < n.  Each (unit,
+// stage) step reads its twiddles as its butterflies need them; with PF the
+// 2^tau twiddles of the next step are loaded while the current step computes.
+template <class G, bool PF = false, class TW>
+LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint32_t qinv) {
+  const int rr = G::r(p);
+  const int nu = G::E >> rr;
+  const uint32_t q2 = 2 * q;
+  uint32_t wc[PF ? G::E / 2 : 1], wn[PF ? G::E / 2 : 1];
+  if (PF) stage_tw<G>(p, t, 0, 0, tw, wc);
+#pragma unroll
+  for (int u = 0; u < nu; ++u) {
 #pragma unroll
     for (int tau = 0; tau < rr; ++tau) {
+      const bool more = tau + 1 < rr || u + 1 < nu;
+      if (PF && more) stage_tw<G>(p, t, tau + 1 < rr ? u : u + 1, tau + 1 < rr ? tau + 1 : 0, tw, wn);
       const int half = 1 << (rr - 1 - tau);
+      const int h = G::s0(p) == 0 ? u : (u * G::T + t) >> (G::LOGN - G::s0(p) - rr);
 #pragma unroll
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
-        const int s = sh + tau;
-        const uint32_t w = tw_get(tw, (uint32_t)((1 << s) + (h << tau) + (c >> (rr - tau))), sh == 0);
+        const uint32_t w = PF ? wc[c >> (rr - tau)]
+                              : tw_get(tw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))),
+                                       G::s0(p) == 0);
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
         uint32_t X = umin(*a, *a - q2);
@@ -131,29 +149,38 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint3
         *b = X + q2 - Tm;
       }
       LRHE_STAGE_FENCE();
+      if (PF && more) {
+#pragma unroll
+        for (int j = 0; j < G::E / 2; ++j) wc[j] = wn[j];
+      }
     }
   }
 }
 
 // One pass of the inverse (Gentleman-Sande) transform; passes run in the order
 // NPASS-1 .. 0 and stages inside a pass from the last to the first.  Values in
-// and out in [0, 2q).  itw: psi^-brv(k) R mod q.
-template <class G, class TW>
+// and out in [0, 2q).  itw: psi^-brv(k) R mod q.  PF as in fwd_pass.
+template <class G, bool PF = false, class TW>
 LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint32_t qinv) {
-  const int rr = G::r(p), sh = G::s0(p);
-  const int lstride = G::LOGN - sh - rr;
+  const int rr = G::r(p);
+  const int nu = G::E >> rr;
   const uint32_t q2 = 2 * q;
+  uint32_t wc[PF ? G::E / 2 : 1], wn[PF ? G::E / 2 : 1];
+  if (PF) stage_tw<G>(p, t, 0, rr - 1, itw, wc);
 #pragma unroll
-  for (int u = 0; u < (G::E >> rr); ++u) {
-    const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
+  for (int u = 0; u < nu; ++u) {
 #pragma unroll
     for (int tau = rr - 1; tau >= 0; --tau) {
+      const bool more = tau > 0 || u + 1 < nu;
+      if (PF && more) stage_tw<G>(p, t, tau > 0 ? u : u + 1, tau > 0 ? tau - 1 : rr - 1, itw, wn);
       const int half = 1 << (rr - 1 - tau);
+      const int h = G::s0(p) == 0 ? u : (u * G::T + t) >> (G::LOGN - G::s0(p) - rr);
 #pragma unroll
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
-        const int s = sh + tau;
-        const uint32_t w = tw_get(itw, (uint32_t)((1 << s) + (h << tau) + (c >> (rr - tau))), sh == 0);
+        const uint32_t w = PF ? wc[c >> (rr - tau)]
+                              : tw_get(itw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))),
+                                       G::s0(p) == 0);
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
         uint32_t U = *a + *b;
@@ -163,6 +190,10 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint
         *b = mulm(V, w, q, qinv);
       }
       LRHE_STAGE_FENCE();
+      if (PF && more) {
+#pragma unroll
+        for (int j = 0; j < G::E / 2; ++j) wc[j] = wn[j];
+      }
     }
   }
 }

@@ -70,3 +70,36 @@ def slot_exponents(n):
     """e_j = 3^j mod 2n for j < n/2, -3^(j - n/2) mod 2n otherwise."""
     e = [pow(3, j, 2 * n) for j in range(n // 2)]
     return e + [(2 * n - x) % (2 * n) for x in e]
+
+
+def is_prime(m):
+    if m < 2:
+        return False
+    for sp in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        if m % sp == 0:
+            return m == sp
+    d, s = m - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        x = pow(a, d, m)
+        if x in (1, m - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % m
+            if x == m - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def ntt_primes(n, count):
+    """The largest primes below 2^30 that are 1 mod 2n."""
+    out, c = [], ((1 << 30) - 1) // (2 * n) * (2 * n) + 1
+    while len(out) < count:
+        if c < (1 << 30) and is_prime(c):
+            out.append(c)
+        c -= 2 * n
+    return out

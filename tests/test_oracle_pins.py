@@ -462,3 +462,13 @@ def test_tiny_two_primes_noise_reading(k_tiny3):
     exp = np.zeros(o.n, dtype=np.int64)
     exp[0] = O.plain_scores(wl.X, wl.W, wl.b, o.t)[0, 0]
     assert budget < 1 and not np.array_equal(z, exp)
+
+
+def test_parameter_sets_are_largest_ntt_primes():
+    """The data primes and special prime of every parameter set are the largest
+    primes below 2^30 that are 1 mod 2n, in decreasing order; t is prime and 1 mod 2n."""
+    from bruteforce import is_prime, ntt_primes
+    for p in WL.PARAMS.values():
+        L = len(p.q)
+        assert list(p.q) + [p.P] == ntt_primes(p.n, L + 1)
+        assert is_prime(p.t) and p.t % (2 * p.n) == 1
