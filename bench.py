@@ -220,7 +220,9 @@ def main():
     ap.add_argument("--rows", type=int, default=512)
     ap.add_argument("--features", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default residues-per-thread choices")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--tune", default="", metavar="KEY=V,...",
+                    help="set launch choices (e.g. large.le_mac=6,large.mac_mode=0) instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one streaming copy-like kernel of this size before the timed steps")
     ap.add_argument("--cpu-rows", type=int, default=16, help="individuals in the oracle's timed sample")
@@ -260,7 +262,11 @@ def main():
     plain = O.plain_scores(wl.X, wl.W, wl.b, p.t)
     # pick residues-per-thread of the transform kernels by timing them on this workload
     ctx.encrypt_rows(keys, Xd, seed=3, out=xct, ws=ws_enc)
-    tuned = ctx.tuning() if args.no_autotune else ctx.autotune_fast(keys, model, xct, rows, out=y, ws=ws)
+    for kv in filter(None, args.tune.split(",")):
+        key, val = kv.split("=")
+        ctx.tune_set(key.strip(), int(val))
+    fixed = args.no_autotune or bool(args.tune)
+    tuned = ctx.tuning() if fixed else ctx.autotune_fast(keys, model, xct, rows, out=y, ws=ws)
     log("tuning", tuned)
 
     def step():
@@ -357,7 +363,8 @@ def main():
         s1 = one_fast()
         assert np.array_equal(s1, O.plain_scores(w1.X, w1.W, w1.b, p.t))
         # the latency-bound tile class (16 pairs) keeps its own launch choices
-        ctx.autotune_fast(keys, m1, x1, 1, out=y1, ws=ws1)
+        if not fixed:
+            ctx.autotune_fast(keys, m1, x1, 1, out=y1, ws=ws1)
         fast_ms = timeit(one_fast, 5)
         fast_srv_ms = timeit(lambda: ctx.matmul_fast(keys, m1, x1, 1, out=y1, ws=ws1), 5)
         fct = ctx.empty_ct(w1.f)

@@ -155,6 +155,7 @@ typedef struct {
   uint32_t rows;
   const lrhe_model* model;
   uint32_t* y;                /* device, ceil(rows classes / n) ciphertexts */
+  const lrhe_gk* gk;          /* the client's Galois keys; NULL = the keys given to run/capture */
 } lrhe_request;
 
 typedef struct lrhe_batch lrhe_batch;
@@ -177,6 +178,10 @@ void lrhe_batch_destroy(lrhe_batch* b);
 int lrhe_server_create(lrhe_ctx* ctx, const lrhe_gk* gk, size_t hbm_budget, lrhe_server** out);
 int lrhe_server_submit(lrhe_server* s, const lrhe_model* model, const uint32_t* xct, uint32_t rows, uint32_t* y,
                        uint64_t* req_id);
+/* The same for a request under another client's keys (gk of the same context,
+ * resident until the request is done); requests of different clients share tiles. */
+int lrhe_server_submit_keys(lrhe_server* s, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct,
+                            uint32_t rows, uint32_t* y, uint64_t* req_id);
 /* done = 1 once the request's outputs are written; latency_s = submit -> completion. */
 int lrhe_server_poll(lrhe_server* s, uint64_t req_id, int* done, double* latency_s);
 /* Block until every admitted request is done. */

@@ -270,15 +270,18 @@ class Context:
 
 
 class Batch:
-    """A fixed set of requests (xct, rows, model, y) planned once; run() executes
-    Algorithm 1 for all of them, capture() records the launches in a hipGraph."""
+    """A fixed set of requests (xct, rows, model, y[, keys]) planned once; run()
+    executes Algorithm 1 for all of them, capture() records the launches in a
+    hipGraph.  A request without its own keys uses the batch's keys."""
 
     def __init__(self, ctx: Context, keys: Keys, requests):
         self.ctx, self.keys = ctx, keys
-        self.requests = list(requests)   # keeps the tensors alive
+        self.requests = list(requests)   # keeps the tensors and keys alive
         arr = (N.LrheRequest * len(self.requests))()
-        for k, (xct, rows, model, y) in enumerate(self.requests):
-            arr[k] = N.LrheRequest(N.ptr(xct), rows, model.handle, N.ptr(y))
+        for k, req in enumerate(self.requests):
+            xct, rows, model, y = req[:4]
+            rkeys = req[4] if len(req) > 4 else None
+            arr[k] = N.LrheRequest(N.ptr(xct), rows, model.handle, N.ptr(y), rkeys.gk if rkeys is not None else None)
         h = ctypes.c_void_p()
         N.check(N.lib().lrhe_batch_create(ctx.h, ctypes.cast(arr, ctypes.c_void_p), len(self.requests),
                                           ctypes.byref(h)))
@@ -319,11 +322,18 @@ class Server:
         N.check(N.lib().lrhe_server_create(ctx.h, keys.gk, hbm_budget, ctypes.byref(h)))
         self.h = h
         self._keep = {}
+        self._held = [keys]   # key sets stay alive while the server may use them
 
-    def submit(self, model: Model, xct, rows: int, y):
-        """Returns the request id, or None when admission is refused (LRHE_EAGAIN)."""
+    def submit(self, model: Model, xct, rows: int, y, keys: Keys = None):
+        """Returns the request id, or None when admission is refused (LRHE_EAGAIN).
+        `keys`: the client's keys when they are not the server's."""
         rid = ctypes.c_uint64()
-        code = N.lib().lrhe_server_submit(self.h, model.handle, N.ptr(xct), rows, N.ptr(y), ctypes.byref(rid))
+        if keys is not None:
+            self._held.append(keys)
+            code = N.lib().lrhe_server_submit_keys(self.h, keys.gk, model.handle, N.ptr(xct), rows, N.ptr(y),
+                                                   ctypes.byref(rid))
+        else:
+            code = N.lib().lrhe_server_submit(self.h, model.handle, N.ptr(xct), rows, N.ptr(y), ctypes.byref(rid))
         if code == N.LRHE_EAGAIN:
             return None
         N.check(code)

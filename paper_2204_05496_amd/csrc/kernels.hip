@@ -462,8 +462,8 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // single-buffered).
 template <int LOGN, int LE, int MODE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
-    DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const uint32_t* __restrict__ key,
-    uint32_t g, uint32_t* __restrict__ ACC) {
+    DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
+    const uint32_t* __restrict__ gk_default, uint32_t gi, uint32_t g, uint32_t* __restrict__ ACC) {
   using G = Geom<LOGN, LE>;
   constexpr bool DB = (MODE & 1) && 2 * G::LDS_WORDS * 4 <= 160 * 1024;
   constexpr bool DP = (MODE & 2) != 0;   // digit prefetch
@@ -486,7 +486,10 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   if constexpr ((MODE & 32) != 0) r = (r + (int)(lp % (L + 1))) % (L + 1);
   const Mod mr = c.mod[r];
   const TwView tw = twv(c.tw, r, G::N);
-  const DBuf kr(key + (size_t)r * L * 2 * G::N, (uint32_t)(L * 2 * G::N));   // [L digits][2][n]
+  // the pair's Galois key for element gi, target modulus r: [L digits][2][n]
+  const uint32_t* gk = pairs[lp].gk;
+  const uint32_t* key = (gk ? gk : gk_default) + (size_t)gi * (L + 1) * L * 2 * G::N;
+  const DBuf kr(key + (size_t)r * L * 2 * G::N, (uint32_t)(L * 2 * G::N));
   const DBuf dp(D + lp * L * G::N, (uint32_t)(L * G::N));
   uint32_t ab[G::E], aa[G::E], x[G::E];
 #pragma unroll
@@ -726,6 +729,7 @@ __global__ __launch_bounds__(256) void k_plan_single(DevCtx c, const uint32_t* x
     d.xrow = xct + i * K * ctw;
     d.wcls = wpt + jc * K * L * n;
     d.dbias = dbias + jc * L;
+    d.gk = nullptr;
     d.K = K;
     d.slot = (uint32_t)(r % n);
     pairs[idx] = d;
@@ -750,8 +754,6 @@ __global__ __launch_bounds__(256) void k_plan_single(DevCtx c, const uint32_t* x
 }
 
 // ------------------------------------------------------------------ standard baseline
-// y[j][x][i] = sum_k fct[k][x][i] w_kj (+ Delta(b_j) for x = 0); one residue per thread,
-// classes in chunks of 16 held in registers, so every input residue is read once per chunk.
 // Standard baseline (one ciphertext per feature, individuals in the slots):
 // y[j] = sum_k fct[k] * w[k][j] + Delta(b_j), coefficient-wise over every word
 // of the ciphertexts (a scalar product commutes with the transform).
@@ -835,7 +837,7 @@ __global__ __launch_bounds__(64 * STD_WAVES) void k_std(DevCtx c, const uint32_t
 // k_ks_mac variants selectable through the "mac_mode" tuning key (index -> MODE bits)
 #ifndef LRHE_MAC_MODES
 #define LRHE_MAC_MODE_CASE(IDX, LN, LE, MODE) \
-  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, key, g, ACC); break;
+  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC); break;
 #define LRHE_MAC_MODES(LN, LE)                                                           \
   LRHE_MAC_MODE_CASE(0, LN, LE, 104) /* one buffer, 2 workgroups/CU, pair per XCD, rotated */ \
   LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
@@ -972,7 +974,6 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
                        uint32_t* ACC, uint32_t* part, hipStream_t s) {
   const uint64_t n = c->n, L = c->L;
   const uint64_t ctw = 2 * L * n;
-  const size_t keyw = (size_t)(L + 1) * L * 2 * n;
   for (uint32_t t = 0, pb = 0; pb < npairs; ++t, pb += B) {
     const uint32_t Bt = min(B, npairs - pb);
     const Knobs& kn = c->tune.knobs(Bt);
@@ -992,7 +993,6 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
     const int steps = (stage >= 2 && stage < 100) ? stage - 2 : (int)c->ngal;
     for (int gi = 0; gi < steps; ++gi) {
       const uint32_t g = c->gal[gi];
-      const uint32_t* key = gk_d + (size_t)gi * keyw;
       {
         ProfScope ps(s, "k_ks_intt");
         LRHE_DISPATCH_LE(c->logn, kn.le_intt, {

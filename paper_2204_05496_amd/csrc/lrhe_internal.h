@@ -47,6 +47,7 @@ struct PairDesc {
   const uint32_t* xrow;   // the K ciphertexts of the row, [K][2][L][n]
   const uint32_t* wcls;   // the K plaintexts of the class, [K][L][n] (Montgomery)
   const uint32_t* dbias;  // Delta(b_class) mod q_i, [L]
+  const uint32_t* gk;     // Galois keys of the pair's client, or null for the launch's default keys
   uint32_t K;             // chunks
   uint32_t slot;          // one-hot slot l = r mod n of the pair
 };

@@ -86,6 +86,7 @@ extern "C" int lrhe_batch_create(lrhe_ctx* c, const lrhe_request* reqs, uint32_t
   for (uint32_t r = 0; r < nreq; ++r) {
     if (!reqs[r].xct || !reqs[r].model || !reqs[r].y || reqs[r].rows == 0)
       return perr(LRHE_EINVAL, "request %u: null buffer or no rows", r);
+    if (reqs[r].gk && !reqs[r].gk->d) return perr(LRHE_EINVAL, "request %u: Galois keys without device copy", r);
     total += (uint64_t)reqs[r].rows * reqs[r].model->classes;
   }
   if (total > 0x7fffffffull) return perr(LRHE_EINVAL, "too many pairs");
@@ -113,6 +114,7 @@ extern "C" int lrhe_batch_create(lrhe_ctx* c, const lrhe_request* reqs, uint32_t
         const uint64_t i = p / m->classes, jc = p % m->classes;
         PairDesc d;
         d.xrow = reqs[r].xct + i * m->K * ctw;
+        d.gk = reqs[r].gk ? reqs[r].gk->d : nullptr;
         d.wcls = m->wpt + jc * m->K * L * n;
         d.dbias = m->dbias + jc * L;
         d.K = m->K;
@@ -240,6 +242,7 @@ struct SReq {
   uint64_t id = 0;
   const uint32_t* xct = nullptr;
   const lrhe_model* m = nullptr;
+  const lrhe_gk* gk = nullptr;      // the client's Galois keys (null: the server's)
   uint32_t* y = nullptr;
   uint64_t npairs = 0, next = 0, nout = 0;
   uint32_t part0 = 0, nparts = 0;   // partial slots [part0, part0 + nparts) of the arena
@@ -359,6 +362,7 @@ void run_tick(lrhe_server* sv, int slot) {
         const uint64_t i = p / m->classes, jc = p % m->classes, o = p / n;
         PairDesc d;
         d.xrow = r->xct + i * m->K * ctw;
+        d.gk = r->gk ? r->gk->d : nullptr;
         d.wcls = m->wpt + jc * m->K * L * n;
         d.dbias = m->dbias + jc * L;
         d.K = m->K;
@@ -501,11 +505,18 @@ extern "C" int lrhe_server_create(lrhe_ctx* c, const lrhe_gk* gk, size_t hbm_bud
 
 extern "C" int lrhe_server_submit(lrhe_server* sv, const lrhe_model* m, const uint32_t* xct, uint32_t rows,
                                   uint32_t* y_out, uint64_t* req_id) {
+  return lrhe_server_submit_keys(sv, nullptr, m, xct, rows, y_out, req_id);
+}
+
+extern "C" int lrhe_server_submit_keys(lrhe_server* sv, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
+                                       uint32_t rows, uint32_t* y_out, uint64_t* req_id) {
   if (!sv || !m || !xct || !y_out || !req_id || rows == 0) return perr(LRHE_EINVAL, "bad argument");
+  if (gk && (!gk->d || gk->words != sv->gk->words)) return perr(LRHE_EINVAL, "Galois keys of another context");
   const uint64_t n = sv->c->n;
   auto* r = new SReq();
   r->xct = xct;
   r->m = m;
+  r->gk = gk;
   r->y = y_out;
   r->npairs = (uint64_t)rows * m->classes;
   r->nout = (r->npairs + n - 1) / n;

@@ -27,7 +27,8 @@ class LrheParams(ctypes.Structure):
 
 
 class LrheRequest(ctypes.Structure):
-    _fields_ = [("xct", ctypes.c_void_p), ("rows", u32), ("model", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+    _fields_ = [("xct", ctypes.c_void_p), ("rows", u32), ("model", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("gk", ctypes.c_void_p)]
 
 
 class LrheError(RuntimeError):
@@ -70,6 +71,7 @@ SIGNATURES = {
     "lrhe_batch_destroy": (None, [vp]),
     "lrhe_server_create": (i32, [vp, vp, sz, ctypes.POINTER(vp)]),
     "lrhe_server_submit": (i32, [vp, vp, vp, u32, vp, ctypes.POINTER(u64)]),
+    "lrhe_server_submit_keys": (i32, [vp, vp, vp, vp, u32, vp, ctypes.POINTER(u64)]),
     "lrhe_server_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
     "lrhe_server_drain": (i32, [vp]),
     "lrhe_server_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32)]),

@@ -167,3 +167,46 @@ def test_uneven_requests_n16k_scores(P, torch):
         assert torch.equal(alone, ys[k]), f"request {k}"
         S, budget = ctx.scores_fast(keys, ys[k], wl.rows, wl.classes)
         assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t)) and budget > 50
+
+
+def test_two_clients_batch_and_server(P, torch):
+    """Requests of two clients (two key sets) share tiles in a batch and in the
+    server: each output equals that client's request run alone, and decrypts
+    under that client's secret key to X W + b mod t."""
+    p = WL.PARAMS["tiny3"]
+    ctx = P.Context.from_params(p, device=0)
+    ctx.tune_set("tile", 64)
+    ka, kb = ctx.keygen(2101), ctx.keygen(2102)
+    specs = [(2, 3000, 4), (5, 700, 8), (1, 4096, 16), (3, 5000, 4)]
+    reqs = []
+    for k, (rows, f, classes) in enumerate(specs):
+        keys = ka if k % 2 == 0 else kb
+        wl = WL.make(f"c{k}", "tiny3", rows, f, classes, 0.02, 700 + 13 * k)
+        xct = ctx.encrypt_rows(keys, wl.X, seed=800 + k)
+        model = ctx.model(wl.W, wl.b)
+        alone = ctx.matmul_fast(keys, model, xct, rows)
+        reqs.append((wl, keys, xct, model, alone))
+    torch.cuda.synchronize()
+    ys = [ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n)) for wl, _, _, _, _ in reqs]
+    b = P.Batch(ctx, ka, [(xct, wl.rows, model, y) + (() if keys is ka else (keys,))
+                          for (wl, keys, xct, model, _), y in zip(reqs, ys)])
+    say("two clients: batch of", b.npairs, "pairs")
+    b.run()
+    torch.cuda.synchronize()
+    for k, ((wl, keys, xct, model, alone), y) in enumerate(zip(reqs, ys)):
+        assert torch.equal(y, alone), f"batch request {k}"
+    srv = P.Server(ctx, ka, hbm_budget=1 << 30)
+    ys2, ids = [], []
+    for k, (wl, keys, xct, model, _) in enumerate(reqs):
+        y = ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n))
+        ys2.append(y)
+        rid = srv.submit(model, xct, wl.rows, y, keys=None if keys is ka else keys)
+        assert rid is not None
+        ids.append(rid)
+    srv.drain()
+    for k, ((wl, keys, xct, model, alone), y) in enumerate(zip(reqs, ys2)):
+        assert srv.poll(ids[k])[0]
+        assert torch.equal(y, alone), f"server request {k}"
+        S, budget = ctx.scores_fast(keys, y, wl.rows, wl.classes)
+        assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t)) and budget > 0
+    srv.close()
