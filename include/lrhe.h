@@ -227,8 +227,8 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * "mac_mode" = variant of the key-switch inner-product kernel: 0 (default):
  * one LDS exchange buffer and two workgroups per CU, the workgroups of a pair
  * on one XCD; 1: as 0 with the twiddles of the next butterfly stage loaded
- * ahead; 2: double-buffered exchange with twiddles ahead; 3: double-buffered
- * exchange with the next digit loaded ahead.  These five keys exist in two
+ * ahead; 2: double-buffered exchange, pair per XCD, unreduced 64-bit inner
+ * products; 3: double-buffered exchange with the next digit loaded ahead.  These five keys exist in two
  * classes, for tiles of fewer than "small_below" pairs (default 1024; such
  * launches are latency-bound) and for larger tiles: "small.<key>" and
  * "large.<key>" address one class, a bare key sets both and reads the large

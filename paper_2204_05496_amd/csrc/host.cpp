@@ -147,8 +147,50 @@ static void host_ntt_t(uint32_t* a, const uint32_t* tw, const Mod& m, bool inver
     for (int i = 0; i < G::N; ++i) a[i] = red1(mulm(tmp[i], m.ninv_m, m.q, m.qinv), m.q);
   }
 }
+// The same transforms as plain in-place loops (forward: Cooley-Tukey with
+// psi^brv(m + i) for block i of a stage with m blocks; inverse: Gentleman-Sande
+// with psi^-brv(m + i), then n^-1).  Both produce the canonical result, so they
+// agree with the pass-structured version bit for bit; this one is several times
+// faster on the host and serves keygen and decryption.
+static void host_ntt_plain(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
+  const uint32_t n = c->n;
+  const Mod& md = c->mods[mi];
+  const uint32_t q = md.q;
+  const uint32_t* tb = (inverse ? c->h_itw.data() : c->h_tw.data()) + (size_t)mi * n;
+  if (!inverse) {
+    for (uint32_t i = 0; i < n; ++i) a[i] = red2(a[i], q);
+    for (uint32_t m = 1, h = n / 2; m < n; m <<= 1, h >>= 1)
+      for (uint32_t i = 0; i < m; ++i) {
+        const uint32_t w = tb[m + i];
+        uint32_t* x = a + (size_t)2 * i * h;
+        for (uint32_t j = 0; j < h; ++j) {
+          const uint32_t u = x[j], v = red1(mulm(x[j + h], w, q, md.qinv), q);
+          x[j] = addm(u, v, q);
+          x[j + h] = subm(u, v, q);
+        }
+      }
+  } else {
+    for (uint32_t i = 0; i < n; ++i) a[i] = red2(a[i], q);
+    for (uint32_t m = n / 2, h = 1; m >= 1; m >>= 1, h <<= 1)
+      for (uint32_t i = 0; i < m; ++i) {
+        const uint32_t w = tb[m + i];
+        uint32_t* x = a + (size_t)2 * i * h;
+        for (uint32_t j = 0; j < h; ++j) {
+          const uint32_t u = x[j], v = x[j + h];
+          x[j] = addm(u, v, q);
+          x[j + h] = red1(mulm(subm(u, v, q), w, q, md.qinv), q);
+        }
+      }
+    for (uint32_t i = 0; i < n; ++i) a[i] = red1(mulm(a[i], md.ninv_m, q, md.qinv), q);
+  }
+}
+
 // forward: natural coefficients (< 4q) -> evaluations, bit-reversed order; inverse: back
 static void host_ntt(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
+  host_ntt_plain(c, mi, a, inverse);
+}
+// the pass-structured version: the kernels' own pass arithmetic, emulated
+static void host_ntt_passes(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
   const uint32_t* tb = (inverse ? c->h_itw.data() : c->h_tw.data()) + (size_t)mi * c->n;
   const Mod& m = c->mods[mi];
   switch (c->logn) {
@@ -587,74 +629,141 @@ static double big_log2(const Big& a) {
   return -INFINITY;
 }
 
+// Fixed-width unsigned integers for the exact rounding of decryption: Q has at
+// most LRHE_MAXL 30-bit primes (450 bits); sums of L terms x_j R_j (Q / q_j)
+// stay below 2^64 Q.  No allocation in the per-coefficient loop.
+namespace {
+constexpr int FW = (LRHE_MAXL * 30 + 64) / 32 + 2;
+struct Fixed {
+  uint32_t w[FW];
+};
+inline void fx_from(Fixed& a, const Big& b) {
+  for (int i = 0; i < FW; ++i) a.w[i] = i < (int)b.size() ? b[i] : 0;
+}
+inline void fx_add_mul(Fixed& acc, const Fixed& a, uint64_t m, int nw) {   // acc += a m (nw words)
+  unsigned __int128 carry = 0;
+  for (int i = 0; i < nw; ++i) {
+    const unsigned __int128 v = (unsigned __int128)a.w[i] * m + acc.w[i] + carry;
+    acc.w[i] = (uint32_t)v;
+    carry = v >> 32;
+  }
+}
+inline int fx_cmp(const Fixed& a, const Fixed& b, int nw) {
+  for (int i = nw; i-- > 0;)
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+  return 0;
+}
+inline void fx_sub(Fixed& a, const Fixed& b, int nw) {   // a -= b, a >= b
+  int64_t borrow = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int64_t v = (int64_t)a.w[i] - b.w[i] - borrow;
+    borrow = v < 0;
+    a.w[i] = (uint32_t)(v + (borrow << 32));
+  }
+}
+inline double fx_log2(const Fixed& a, int nw) {
+  for (int i = nw; i-- > 0;)
+    if (a.w[i]) {
+      const double hi = a.w[i], lo = i > 0 ? a.w[i - 1] : 0;
+      return std::log2(hi + lo / 4294967296.0) + 32.0 * i;
+    }
+  return -INFINITY;
+}
+}  // namespace
+
 static int decrypt_host(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* h, uint32_t count, int64_t* slots,
                         double* budgets) {
   const uint32_t n = c->n, L = c->L, t = c->t;
   const size_t ctw = (size_t)2 * L * n;
-  Big Qhalf = c->Qbig;   // floor(Q / 2)
+  Fixed Q, Qhalf, Qhat[LRHE_MAXL];
+  fx_from(Q, c->Qbig);
+  Qhalf = Q;   // floor(Q / 2)
   {
     uint32_t carry = 0;
-    for (size_t i = Qhalf.size(); i-- > 0;) {
-      const uint64_t v = ((uint64_t)carry << 32) | Qhalf[i];
-      Qhalf[i] = (uint32_t)(v >> 1);
+    for (int i = FW; i-- > 0;) {
+      const uint64_t v = ((uint64_t)carry << 32) | Qhalf.w[i];
+      Qhalf.w[i] = (uint32_t)(v >> 1);
       carry = (uint32_t)(v & 1);
     }
   }
-  for (uint32_t ci = 0; ci < count; ++ci) {
+  for (uint32_t j = 0; j < L; ++j) fx_from(Qhat[j], c->Qhat[j]);
+  // words that hold 2^64 Q: sums of L terms below 2^64 Q, and k0 Q
+  const int nw = std::min(FW, (int)((c->log2Q + 66) / 32) + 2);
+  int bad = 0;
+  // one ciphertext: x_j = [c0 + c1 s]_{q_j} in coefficient form, then
+  // m = sum_j x_j I_j + round(sum_j x_j R_j / q_j) mod t with the rounding done
+  // exactly: N = sum_j x_j R_j (Q/q_j), k0 = round(N / Q), noise w = N - k0 Q
+  auto one = [&](uint32_t ci, uint32_t* X, uint32_t* mcoef, bool inner_parallel) -> int {
     const uint32_t* C = &h[(size_t)ci * ctw];
-    // x_j = [c0 + c1 s]_{q_j}, coefficient form
-    std::vector<uint32_t> X((size_t)L * n);
-    for (uint32_t j = 0; j < L; ++j) {
+#pragma omp parallel for schedule(static) if (inner_parallel)
+    for (int j = 0; j < (int)L; ++j) {
       const uint64_t q = c->q[j];
       const uint32_t* Sj = &sk->S[(size_t)j * n];
       uint32_t* xj = &X[(size_t)j * n];
       for (uint32_t k = 0; k < n; ++k) xj[k] = (uint32_t)((C[(size_t)j * n + k] + (uint64_t)C[(size_t)(L + j) * n + k] * Sj[k]) % q);
-      host_ntt(c, (int)j, xj, true);
+      host_ntt(c, j, xj, true);
     }
-    // m = sum_j x_j I_j + round(sum_j x_j R_j / q_j) mod t, with the rounding done
-    // exactly: N = sum_j x_j R_j (Q/q_j), k0 = round(N / Q), noise w = N - k0 Q
-    std::vector<uint32_t> mcoef(n);
     double worst = -INFINITY;
-    for (uint32_t k = 0; k < n; ++k) {
+    int err = 0;
+#pragma omp parallel for schedule(static) reduction(max : worst) reduction(| : err) if (inner_parallel)
+    for (int k = 0; k < (int)n; ++k) {
       uint64_t mi = 0;
       double approx = 0;
-      Big N;
+      Fixed N{};
       for (uint32_t j = 0; j < L; ++j) {
         const uint64_t xj = X[(size_t)j * n + k];
         mi = (mi + xj % t * c->dec_I[j]) % t;
         approx += (double)xj * c->dec_Rf[j];
-        big_add_mul(N, c->Qhat[j], xj * c->dec_R[j]);
+        fx_add_mul(N, Qhat[j], xj * c->dec_R[j], nw);
       }
       int64_t k0 = (int64_t)std::floor(approx) - 1;
       if (k0 < 0) k0 = 0;
-      Big K0Q;
-      big_add_mul(K0Q, c->Qbig, (uint64_t)k0);
-      if (big_cmp(N, K0Q) < 0) return fail(LRHE_EINVAL, "decrypt: rounding estimate out of range");
-      big_sub(N, K0Q);   // N - k0 Q >= 0
+      Fixed K0Q{};
+      fx_add_mul(K0Q, Q, (uint64_t)k0, nw);
+      if (fx_cmp(N, K0Q, nw) < 0) {
+        err = 1;
+        continue;
+      }
+      fx_sub(N, K0Q, nw);   // N - k0 Q >= 0
       int guard = 0;
-      while (big_cmp(N, Qhalf) > 0 && guard++ < 8) {   // keep |w| <= Q/2
-        if (big_cmp(N, c->Qbig) >= 0) {
-          big_sub(N, c->Qbig);
+      while (fx_cmp(N, Qhalf, nw) > 0 && guard++ < 8) {   // keep |w| <= Q/2
+        if (fx_cmp(N, Q, nw) >= 0) {
+          fx_sub(N, Q, nw);
           ++k0;
         } else {   // Q/2 < N < Q: w = N - Q is negative
-          Big tmp = c->Qbig;
-          big_sub(tmp, N);
+          Fixed tmp = Q;
+          fx_sub(tmp, N, nw);
           N = tmp;
           ++k0;
           break;
         }
       }
-      worst = std::max(worst, big_log2(N));
+      worst = std::max(worst, fx_log2(N, nw));
       mcoef[k] = (uint32_t)((mi + (uint64_t)(k0 % t)) % t);
     }
+    if (err) return 1;
     // decode: slot j = evaluation at psi_t^(e_j)
-    host_ntt(c, (int)L + 1, mcoef.data(), false);
+    host_ntt(c, (int)L + 1, mcoef, false);
     for (uint32_t j = 0; j < n; ++j) {
       const uint32_t v = mcoef[c->slot_pos[j]];
       slots[(size_t)ci * n + j] = v > (t - 1) / 2 ? (int64_t)v - t : (int64_t)v;
     }
     if (budgets) budgets[ci] = (c->log2Q - 1.0) - worst;
+    return 0;
+  };
+  if (count == 1) {
+    std::vector<uint32_t> X((size_t)L * n), mcoef(n);
+    bad = one(0, X.data(), mcoef.data(), true);
+  } else {
+    // several ciphertexts: one per thread
+#pragma omp parallel reduction(| : bad)
+    {
+      std::vector<uint32_t> X((size_t)L * n), mcoef(n);
+#pragma omp for schedule(dynamic, 1)
+      for (int ci = 0; ci < (int)count; ++ci) bad |= one((uint32_t)ci, X.data(), mcoef.data(), false);
+    }
   }
+  if (bad) return fail(LRHE_EINVAL, "decrypt: rounding estimate out of range");
   return LRHE_OK;
 }
 
@@ -677,7 +786,7 @@ extern "C" int lrhe_decrypt_slots_host(lrhe_ctx* c, const lrhe_sk* sk, const uin
 
 extern "C" int lrhe_host_transform(lrhe_ctx* c, uint32_t mod_index, uint32_t* a, int inverse) {
   if (!c || !a || mod_index > c->L + 1) return fail(LRHE_EINVAL, "bad argument");
-  host_ntt(c, (int)mod_index, a, inverse != 0);
+  host_ntt_passes(c, (int)mod_index, a, inverse != 0);
   return LRHE_OK;
 }
 

@@ -202,6 +202,12 @@ __device__ __forceinline__ u32x4 ld4L(const DBuf& g, uint32_t base, int e) {
   }
 }
 
+// x = hi 2^32 + lo is congruent to hi (2^32 mod q) + lo (r1 = 2^32 mod q), which
+// is below 2^61 + 2^32 for q < 2^30
+__device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r1) {
+  return (uint64_t)(uint32_t)(x >> 32) * r1 + (uint32_t)x;
+}
+
 // lazy accumulate: a, v in [0, 2q) -> [0, 2q)
 __device__ __forceinline__ uint32_t acc2(uint32_t a, uint32_t v, uint32_t q) {
   const uint32_t s = a + v;
@@ -459,7 +465,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // LDS; 2 = the next digit is loaded during the current transform; 4 = the
 // twiddles of the next butterfly stage are loaded during the current one;
 // 8 = a register cap that lets two workgroups share a CU (only useful
-// single-buffered).
+// single-buffered); 128 = the inner products accumulate unreduced 64-bit
+// products (one multiply-add each, folded every 4 digits) instead of reducing
+// every product.
 template <int LOGN, int LE, int MODE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
     DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
@@ -468,6 +476,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   constexpr bool DB = (MODE & 1) && 2 * G::LDS_WORDS * 4 <= 160 * 1024;
   constexpr bool DP = (MODE & 2) != 0;   // digit prefetch
   constexpr bool PF = (MODE & 4) != 0;   // twiddle prefetch
+  constexpr bool A64 = (MODE & 128) != 0;
   __shared__ uint32_t lds[(DB ? 2 : 1) * G::LDS_WORDS];
   int par = 0;
   const int L = c.L;
@@ -492,8 +501,13 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   const DBuf kr(key + (size_t)r * L * 2 * G::N, (uint32_t)(L * 2 * G::N));
   const DBuf dp(D + lp * L * G::N, (uint32_t)(L * G::N));
   uint32_t ab[G::E], aa[G::E], x[G::E];
+  [[maybe_unused]] uint64_t ab64[A64 ? G::E : 1], aa64[A64 ? G::E : 1];
+  [[maybe_unused]] const uint32_t r1 = red1(redc(mr.r2, mr.q, mr.qinv), mr.q);   // 2^32 mod r
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) ab[e] = aa[e] = 0;
+  for (int e = 0; e < G::E; ++e) {
+    if constexpr (A64) ab64[e] = aa64[e] = 0;
+    else ab[e] = aa[e] = 0;
+  }
   // digits are transformed in order i = 0..L-1 (i != r); the next one is
   // prefetched into xn while the current transform runs
   [[maybe_unused]] uint32_t xn[DP ? G::E : 1];
@@ -533,14 +547,44 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
 #pragma unroll
     for (int e = 0; e < G::E; e += 4) {
       const u32x4 vb = ld4L<G>(kr, kb, e), va = ld4L<G>(kr, ka, e);
-      ab[e] = acc2(ab[e], mulm(x[e], vb.x, mr.q, mr.qinv), mr.q);
-      ab[e + 1] = acc2(ab[e + 1], mulm(x[e + 1], vb.y, mr.q, mr.qinv), mr.q);
-      ab[e + 2] = acc2(ab[e + 2], mulm(x[e + 2], vb.z, mr.q, mr.qinv), mr.q);
-      ab[e + 3] = acc2(ab[e + 3], mulm(x[e + 3], vb.w, mr.q, mr.qinv), mr.q);
-      aa[e] = acc2(aa[e], mulm(x[e], va.x, mr.q, mr.qinv), mr.q);
-      aa[e + 1] = acc2(aa[e + 1], mulm(x[e + 1], va.y, mr.q, mr.qinv), mr.q);
-      aa[e + 2] = acc2(aa[e + 2], mulm(x[e + 2], va.z, mr.q, mr.qinv), mr.q);
-      aa[e + 3] = acc2(aa[e + 3], mulm(x[e + 3], va.w, mr.q, mr.qinv), mr.q);
+      if constexpr (A64) {
+        // x < q_r and key words < q_r: each product < 2^60
+        ab64[e] += (uint64_t)x[e] * vb.x;
+        ab64[e + 1] += (uint64_t)x[e + 1] * vb.y;
+        ab64[e + 2] += (uint64_t)x[e + 2] * vb.z;
+        ab64[e + 3] += (uint64_t)x[e + 3] * vb.w;
+        aa64[e] += (uint64_t)x[e] * va.x;
+        aa64[e + 1] += (uint64_t)x[e + 1] * va.y;
+        aa64[e + 2] += (uint64_t)x[e + 2] * va.z;
+        aa64[e + 3] += (uint64_t)x[e + 3] * va.w;
+      } else {
+        ab[e] = acc2(ab[e], mulm(x[e], vb.x, mr.q, mr.qinv), mr.q);
+        ab[e + 1] = acc2(ab[e + 1], mulm(x[e + 1], vb.y, mr.q, mr.qinv), mr.q);
+        ab[e + 2] = acc2(ab[e + 2], mulm(x[e + 2], vb.z, mr.q, mr.qinv), mr.q);
+        ab[e + 3] = acc2(ab[e + 3], mulm(x[e + 3], vb.w, mr.q, mr.qinv), mr.q);
+        aa[e] = acc2(aa[e], mulm(x[e], va.x, mr.q, mr.qinv), mr.q);
+        aa[e + 1] = acc2(aa[e + 1], mulm(x[e + 1], va.y, mr.q, mr.qinv), mr.q);
+        aa[e + 2] = acc2(aa[e + 2], mulm(x[e + 2], va.z, mr.q, mr.qinv), mr.q);
+        aa[e + 3] = acc2(aa[e + 3], mulm(x[e + 3], va.w, mr.q, mr.qinv), mr.q);
+      }
+    }
+    if constexpr (A64) {
+      // every 4 digits: below 2^61 + 2^32 + 4 2^60 < 2^64 before the fold
+      if ((i & 3) == 3) {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) {
+          ab64[e] = fold32(ab64[e], r1);
+          aa64[e] = fold32(aa64[e], r1);
+        }
+      }
+    }
+  }
+  if constexpr (A64) {
+    // fold: < 2^61 + 2^32, so redc lands below 2^29 + q < 4q; keys carry R
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) {
+      ab[e] = red2(redc(fold32(ab64[e], r1), mr.q, mr.qinv), mr.q);
+      aa[e] = red2(redc(fold32(aa64[e], r1), mr.q, mr.qinv), mr.q);
     }
   }
   const int t = tid_fresh();
@@ -766,9 +810,6 @@ __global__ __launch_bounds__(256) void k_plan_single(DevCtx c, const uint32_t* x
 // lo(x) is congruent to x and below 2^61 + 2^32.
 constexpr int STD_WAVES = 8, STD_UNROLL = 8, STD_CJ = 16;
 static_assert(STD_CJ == 16, "std_class_pad pads to 16 classes");
-__device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r1) {
-  return (uint64_t)(uint32_t)(x >> 32) * r1 + (uint32_t)x;
-}
 __global__ __launch_bounds__(64 * STD_WAVES) void k_std(DevCtx c, const uint32_t* __restrict__ fct,
                                                         const uint32_t* __restrict__ wst,
                                                         const uint32_t* __restrict__ dbias, uint32_t f,
@@ -841,7 +882,7 @@ __global__ __launch_bounds__(64 * STD_WAVES) void k_std(DevCtx c, const uint32_t
 #define LRHE_MAC_MODES(LN, LE)                                                           \
   LRHE_MAC_MODE_CASE(0, LN, LE, 104) /* one buffer, 2 workgroups/CU, pair per XCD, rotated */ \
   LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
-  LRHE_MAC_MODE_CASE(2, LN, LE, 37)  /* double buffer, twiddle prefetch, rotated */           \
+  LRHE_MAC_MODE_CASE(2, LN, LE, 225) /* double buffer, pair per XCD, rotated, 64-bit MAC */   \
   LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */
 #endif
 #define LRHE_DISPATCH(LOGNVAR, ...)                          \
