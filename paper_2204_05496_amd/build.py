@@ -13,7 +13,10 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "liblrhe.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "host.cpp", "prof.cpp", "plan.cpp"]
+# (source, object, extra flags): the key-switch launchers build once per ring dimension
+SOURCES = [("kernels.hip", "kernels.hip.o", []), ("host.cpp", "host.cpp.o", []), ("prof.cpp", "prof.cpp.o", []),
+           ("plan.cpp", "plan.cpp.o", [])] + \
+          [("ks_step.hip", f"ks_step.ln{ln}.o", [f"-DLRHE_KS_LOGN={ln}"]) for ln in range(10, 16)]
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
     # packed FP32 instructions stay off in every device compile
@@ -33,21 +36,22 @@ def _stale(obj: str, src: str) -> bool:
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def _compile(src: str, force: bool = False) -> str:
-    obj = os.path.join(BUILD, src + ".o")
+def _compile(entry, force: bool = False) -> str:
+    src, oname, extra = entry
+    obj = os.path.join(BUILD, oname)
     if not force and not _stale(obj, src):
         return obj
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed for {src} {' '.join(extra)}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
 def build(verbose: bool = False, force: bool = False) -> str:
     """Compile (objects whose sources or headers changed, or all with force) and link."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), max(2, os.cpu_count() or 2))) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
     tmp = OUT + ".tmp"
     cmd = ["hipcc", "-shared", "-fopenmp", "--offload-arch=gfx950", *objs, "-o", tmp]

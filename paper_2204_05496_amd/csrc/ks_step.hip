@@ -1,0 +1,82 @@
+// ks_step.hip -- launchers of the rotate-and-accumulate steps (key switching)
+// and of the mask for one ring dimension.  Compiled once per log2 n with
+// -DLRHE_KS_LOGN=<10..15>, so the many instantiations of the transform kernels
+// build in parallel.
+#include "kernels_dev.h"
+
+#ifndef LRHE_KS_LOGN
+#error "compile once per ring dimension with -DLRHE_KS_LOGN=<log2 n>"
+#endif
+
+namespace lrhe {
+
+// residues-per-thread choices available at ring dimension 2^LN (at most 1024
+// threads per workgroup; 16 residues up to n = 16384, 64 from n = 4096)
+template <int LN, int LE>
+constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN < 12);
+
+#define LRHE_LE_SWITCH(LEVAR, ...)                                         \
+  switch (LEVAR) {                                                         \
+    case 4: { constexpr int LE = 4; if constexpr (le_ok<LN, 4>) { __VA_ARGS__; } else { return hipErrorInvalidValue; } } break; \
+    case 5: { constexpr int LE = 5; if constexpr (le_ok<LN, 5>) { __VA_ARGS__; } else { return hipErrorInvalidValue; } } break; \
+    case 6: { constexpr int LE = 6; if constexpr (le_ok<LN, 6>) { __VA_ARGS__; } else { return hipErrorInvalidValue; } } break; \
+    default: return hipErrorInvalidValue;                                  \
+  }
+
+// k_ks_mac variants selectable through the "mac_mode" tuning key (index -> MODE bits)
+#ifndef LRHE_MAC_MODES
+#define LRHE_MAC_MODE_CASE(IDX, LN, LE, MODE) \
+  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC); break;
+#define LRHE_MAC_MODES(LN, LE)                                                           \
+  LRHE_MAC_MODE_CASE(0, LN, LE, 104) /* one buffer, 2 workgroups/CU, pair per XCD, rotated */ \
+  LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
+  LRHE_MAC_MODE_CASE(2, LN, LE, 225) /* double buffer, pair per XCD, rotated, 64-bit MAC */   \
+  LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */
+#endif
+
+template <int LN>
+hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp, const uint32_t* gk_d, uint32_t Bt,
+                          uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint32_t* nxt, hipStream_t s) {
+  const uint32_t L = c->L, g = c->gal[gi];
+  {
+    ProfScope ps(s, "k_ks_intt");
+    LRHE_LE_SWITCH(kn.le_intt, {
+      k_ks_intt<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, g, D);
+    });
+  }
+  {
+    ProfScope ps(s, "k_ks_mac");
+    LRHE_LE_SWITCH(kn.le_mac, {
+      const unsigned grid = (unsigned)(Bt * (L + 1));
+      switch (kn.mac_mode) {
+        LRHE_MAC_MODES(LN, LE)
+        default: return hipErrorInvalidValue;
+      }
+    });
+  }
+  {
+    ProfScope ps(s, "k_ks_moddown");
+    LRHE_LE_SWITCH(kn.le_moddown, {
+      k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt);
+    });
+  }
+  return hipGetLastError();
+}
+
+template <int LN>
+hipError_t launch_mask_step(const lrhe_ctx* c, const Knobs& kn, const uint32_t* cur, const PairDesc* tp,
+                            const GroupDesc* tg, uint32_t ngt, int mode, uint32_t* dst, hipStream_t s) {
+  const uint32_t L = c->L;
+  LRHE_LE_SWITCH(kn.le_mask, {
+    k_mask<LN, LE><<<(unsigned)(ngt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, tp, tg, mode, dst);
+  });
+  return hipGetLastError();
+}
+
+template hipError_t launch_ks_step<LRHE_KS_LOGN>(const lrhe_ctx*, const Knobs&, const PairDesc*, const uint32_t*,
+                                                 uint32_t, uint32_t, const uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                                 hipStream_t);
+template hipError_t launch_mask_step<LRHE_KS_LOGN>(const lrhe_ctx*, const Knobs&, const uint32_t*, const PairDesc*,
+                                                   const GroupDesc*, uint32_t, int, uint32_t*, hipStream_t);
+
+}  // namespace lrhe

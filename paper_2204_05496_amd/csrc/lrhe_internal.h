@@ -166,6 +166,15 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
 // Descriptor-driven Algorithm 1 over pairs[0, npairs) (device arrays): tiles of B
 // pairs; groups[tile_g0[t] .. tile_g0[t+1]) belong to tile t; stage as in
 // lrhe_matmul_fast_pairs (-1 = full: mask into partials, then compress outs).
+// per-ring-dimension launchers (ks_step.hip, one object per log2 n): one
+// rotate-and-accumulate step (k_ks_intt, k_ks_mac, k_ks_moddown) on a tile,
+// and the bias + mask + group sums of a tile
+template <int LN>
+hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp, const uint32_t* gk_d, uint32_t Bt,
+                          uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint32_t* nxt, hipStream_t s);
+template <int LN>
+hipError_t launch_mask_step(const lrhe_ctx* c, const Knobs& kn, const uint32_t* cur, const PairDesc* tp,
+                            const GroupDesc* tg, uint32_t ngt, int mode, uint32_t* dst, hipStream_t s);
 hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* pairs, uint32_t npairs,
                        const GroupDesc* groups, const uint32_t* tile_g0, uint32_t B, const OutDesc* outs,
                        uint32_t nouts, int stage, uint32_t* out, uint32_t* cA, uint32_t* cB, uint32_t* D,

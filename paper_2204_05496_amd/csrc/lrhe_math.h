@@ -103,6 +103,10 @@ struct Geom {
 // per-lane path and a wave-uniform (scalar-load) path.  In the pass that
 // starts at stage 0 the block index h equals u, so its twiddles are uniform.
 LRHE_HD uint32_t tw_get(const uint32_t* tw, uint32_t i, bool) { return tw[i]; }
+// b w_i mod q in [0, 2q) for a twiddle table of Montgomery words w_i R
+LRHE_HD uint32_t tw_mul(const uint32_t* tw, uint32_t i, bool, uint32_t b, uint32_t q, uint32_t qinv) {
+  return mulm(b, tw[i], q, qinv);
+}
 
 // Twiddles of one (unit u, stage tau) step of a pass: the 2^tau distinct values
 // w[j] = tw[2^(s0 + tau) + h 2^tau + j], h the unit's block index.
@@ -126,32 +130,36 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint3
   const int nu = G::E >> rr;
   const uint32_t q2 = 2 * q;
   uint32_t wc[PF ? G::E / 2 : 1], wn[PF ? G::E / 2 : 1];
-  if (PF) stage_tw<G>(p, t, 0, 0, tw, wc);
+  if constexpr (PF) stage_tw<G>(p, t, 0, 0, tw, wc);
 #pragma unroll
   for (int u = 0; u < nu; ++u) {
 #pragma unroll
     for (int tau = 0; tau < rr; ++tau) {
       const bool more = tau + 1 < rr || u + 1 < nu;
-      if (PF && more) stage_tw<G>(p, t, tau + 1 < rr ? u : u + 1, tau + 1 < rr ? tau + 1 : 0, tw, wn);
+      if constexpr (PF) {
+        if (more) stage_tw<G>(p, t, tau + 1 < rr ? u : u + 1, tau + 1 < rr ? tau + 1 : 0, tw, wn);
+      }
       const int half = 1 << (rr - 1 - tau);
       const int h = G::s0(p) == 0 ? u : (u * G::T + t) >> (G::LOGN - G::s0(p) - rr);
 #pragma unroll
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
-        const uint32_t w = PF ? wc[c >> (rr - tau)]
-                              : tw_get(tw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))),
-                                       G::s0(p) == 0);
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
         uint32_t X = umin(*a, *a - q2);
-        uint32_t Tm = mulm(*b, w, q, qinv);
+        const uint32_t Tm =
+            PF ? mulm(*b, wc[c >> (rr - tau)], q, qinv)
+               : tw_mul(tw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))), G::s0(p) == 0, *b,
+                        q, qinv);
         *a = X + Tm;
         *b = X + q2 - Tm;
       }
       LRHE_STAGE_FENCE();
-      if (PF && more) {
+      if constexpr (PF) {
+        if (more) {
 #pragma unroll
-        for (int j = 0; j < G::E / 2; ++j) wc[j] = wn[j];
+          for (int j = 0; j < G::E / 2; ++j) wc[j] = wn[j];
+        }
       }
     }
   }
@@ -166,33 +174,36 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint
   const int nu = G::E >> rr;
   const uint32_t q2 = 2 * q;
   uint32_t wc[PF ? G::E / 2 : 1], wn[PF ? G::E / 2 : 1];
-  if (PF) stage_tw<G>(p, t, 0, rr - 1, itw, wc);
+  if constexpr (PF) stage_tw<G>(p, t, 0, rr - 1, itw, wc);
 #pragma unroll
   for (int u = 0; u < nu; ++u) {
 #pragma unroll
     for (int tau = rr - 1; tau >= 0; --tau) {
       const bool more = tau > 0 || u + 1 < nu;
-      if (PF && more) stage_tw<G>(p, t, tau > 0 ? u : u + 1, tau > 0 ? tau - 1 : rr - 1, itw, wn);
+      if constexpr (PF) {
+        if (more) stage_tw<G>(p, t, tau > 0 ? u : u + 1, tau > 0 ? tau - 1 : rr - 1, itw, wn);
+      }
       const int half = 1 << (rr - 1 - tau);
       const int h = G::s0(p) == 0 ? u : (u * G::T + t) >> (G::LOGN - G::s0(p) - rr);
 #pragma unroll
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
-        const uint32_t w = PF ? wc[c >> (rr - tau)]
-                              : tw_get(itw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))),
-                                       G::s0(p) == 0);
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
         uint32_t U = *a + *b;
         U = umin(U, U - q2);
         uint32_t V = *a + q2 - *b;
         *a = U;
-        *b = mulm(V, w, q, qinv);
+        *b = PF ? mulm(V, wc[c >> (rr - tau)], q, qinv)
+                : tw_mul(itw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))), G::s0(p) == 0, V,
+                         q, qinv);
       }
       LRHE_STAGE_FENCE();
-      if (PF && more) {
+      if constexpr (PF) {
+        if (more) {
 #pragma unroll
-        for (int j = 0; j < G::E / 2; ++j) wc[j] = wn[j];
+          for (int j = 0; j < G::E / 2; ++j) wc[j] = wn[j];
+        }
       }
     }
   }
