@@ -58,8 +58,8 @@ def ks_mac_modmuls(n, L, pairs):
     return pairs * (L * per_q + per_p)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ks_mac_traffic_batch_512x40000x16.txt")
-KERNEL_SOURCES = ("kernels.hip", "lrhe_math.h", "lrhe_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ks_mac_traffic_batch_512x40000x16_le{le}_mode{mode}.txt")
+KERNEL_SOURCES = ("kernels_dev.h", "ks_step.hip", "kernels.hip", "lrhe_math.h", "lrhe_internal.h")
 
 
 def kernel_source_digest():
@@ -76,7 +76,8 @@ def counted_traffic(le_mac, mac_mode):
     summary, already scaled by the copy-kernel calibration; None when the kernel
     sources or its launch variant differ from those the counters saw."""
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+        path = TRAFFIC_FILE.format(le=le_mac, mode=mac_mode)
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
