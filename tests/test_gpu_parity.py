@@ -228,12 +228,25 @@ def test_batch_512x40k_launch_config(n16k, torch):
     plain = O.plain_scores(wl.X, wl.W, wl.b, n16k.p.t)
     assert np.array_equal(S, plain) and budget > 30
     say("batch sampled pairs")
-    sample = [0, 1, 4095, 4096, 8191]
+    # every pair's masked ciphertext, in the same tiles of 4096 pairs as the
+    # compressed run above; sampled pairs (tile edges included) against the oracle
+    npairs = wl.rows * wl.classes
+    allp = ctx.matmul_fast_pairs(n16k.keys, model, xct, wl.rows, 0, npairs, 0)
+    torch.cuda.synchronize()
+    sample = [0, 1, 4095, 4096, 5000, 8191]
     wo = o.encode_weights(wl.W)
     rows_needed = sorted({r // wl.classes for r in sample})
     xo = {i: o.encrypt_rows(n16k.ko, wl.X[i:i + 1], seed=3, row0=i)[0] for i in rows_needed}
     for r in sample:
-        got = n16k.coeff(ctx.matmul_fast_pairs(n16k.keys, model, xct, wl.rows, r, 1, 0))[0]
+        got = n16k.coeff(allp[r:r + 1])[0]
         i, j = divmod(r, wl.classes)
         ref = o.pair(n16k.ko, xo[i], wo[j], int(wl.b[j]), r % o.n, 0)
         assert np.array_equal(got, ref), f"pair {r}"
+    # compression: the masked pairs of the output sum, limb by limb mod q_i, to y
+    acc = torch.zeros((2, ctx.L, ctx.n), dtype=torch.int64, device=allp.device)
+    for c0 in range(0, npairs, 1024):
+        acc += allp[c0:c0 + 1024].to(torch.int64).sum(dim=0)
+    q = torch.tensor(list(n16k.p.q), dtype=torch.int64, device=allp.device).view(1, -1, 1)
+    assert torch.equal(acc % q, y[0].to(torch.int64))
+    del allp, acc
+    torch.cuda.empty_cache()
