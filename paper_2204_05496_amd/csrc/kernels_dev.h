@@ -43,6 +43,22 @@ struct DBuf {
   __device__ __forceinline__ void st4(uint32_t i, u32x4 v) const {
     __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(i * 4u), 0, 0);
   }
+  // word vi + si: vi per lane (a VGPR), si wave-uniform (the SGPR offset of the
+  // instruction), so per-element constants cost no vector instruction.  The
+  // hardware range check covers the per-lane part only: callers keep vi + si
+  // inside the buffer.
+  __device__ __forceinline__ uint32_t at(uint32_t vi, uint32_t si) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)(vi * 4u), (int)(si * 4u), 0);
+  }
+  __device__ __forceinline__ u32x4 at4(uint32_t vi, uint32_t si) const {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)(vi * 4u), (int)(si * 4u), 0);
+  }
+  __device__ __forceinline__ void put(uint32_t vi, uint32_t si, uint32_t v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)(vi * 4u), (int)(si * 4u), 0);
+  }
+  __device__ __forceinline__ void put4(uint32_t vi, uint32_t si, u32x4 v) const {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(vi * 4u), (int)(si * 4u), 0);
+  }
 };
 
 // twiddle table of modulus mi (forward or inverse): per-lane reads through the
@@ -88,24 +104,22 @@ __device__ __forceinline__ uint32_t auto_perm(uint32_t k, uint32_t g, int logn) 
 // buffered (DB = true, two LDS buffers, `par` selects one and flips): the
 // write-after-read barrier is not needed, because consecutive exchanges use
 // different buffers and the barrier of the exchange in between orders them.
+// Addresses: one padded per-thread base per side, constant element offsets.
 template <class G, bool DB = false>
 __device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x, int t, int* par = nullptr) {
   if constexpr (DB) {
     lds += (*par) * G::LDS_WORDS;
     *par ^= 1;
-#pragma unroll
-    for (int e = 0; e < G::E; ++e) lds[G::pad(G::idx(pfrom, t, e))] = x[e];
+  } else {
     __syncthreads();
-#pragma unroll
-    for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(G::idx(pto, t, e))];
-    return;
   }
-  __syncthreads();
+  uint32_t* wr = lds + G::pad(G::tbase(pfrom, t));
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) lds[G::pad(G::idx(pfrom, t, e))] = x[e];
+  for (int e = 0; e < G::E; ++e) wr[G::padoff(G::eoff(pfrom, e))] = x[e];
   __syncthreads();
+  const uint32_t* rd = lds + G::pad(G::tbase(pto, t));
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(G::idx(pto, t, e))];
+  for (int e = 0; e < G::E; ++e) x[e] = rd[G::padoff(G::eoff(pto, e))];
 }
 
 // forward transform: x in pass-0 layout with values < 4q; returns the
@@ -153,60 +167,70 @@ __device__ __forceinline__ uint32_t idxLf(int e) { return idxL<G>(e, tid_fresh()
 
 
 template <class G>
-__device__ __forceinline__ void load0(const DBuf& g, uint32_t* x, int t) {
+__device__ __forceinline__ void load0(const DBuf& g, uint32_t* x, int t, uint32_t s = 0) {
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = g[idx0<G>(e, t)];
+  for (int e = 0; e < G::E; ++e) x[e] = g.at((uint32_t)t, s + G::eoff(0, e));
 }
 template <class G>
 __device__ __forceinline__ void store0(const DBuf& g, const uint32_t* x, int t) {
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) g.st(idx0<G>(e, t), x[e]);
+  for (int e = 0; e < G::E; ++e) g.put((uint32_t)t, G::eoff(0, e), x[e]);
 }
 // last-pass layout: contiguous chunks of 2^r_last residues; vector access when possible
 template <class G>
 __device__ __forceinline__ void loadL(const DBuf& g, uint32_t* x, int t) {
   constexpr int C = 1 << G::r(G::NPASS - 1);
+  const uint32_t b = G::tbase(G::NPASS - 1, t);
   if constexpr (C % 4 == 0) {
 #pragma unroll
     for (int e = 0; e < G::E; e += 4) {
-      const u32x4 v = g.ld4(idxL<G>(e, t));
+      const u32x4 v = g.at4(b, G::eoff(G::NPASS - 1, e));
       x[e] = v.x; x[e + 1] = v.y; x[e + 2] = v.z; x[e + 3] = v.w;
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) x[e] = g[idxL<G>(e, t)];
+    for (int e = 0; e < G::E; ++e) x[e] = g.at(b, G::eoff(G::NPASS - 1, e));
   }
 }
 template <class G>
 __device__ __forceinline__ void storeL(const DBuf& g, const uint32_t* x, int t) {
   constexpr int C = 1 << G::r(G::NPASS - 1);
+  const uint32_t b = G::tbase(G::NPASS - 1, t);
   if constexpr (C % 4 == 0) {
 #pragma unroll
     for (int e = 0; e < G::E; e += 4) {
       u32x4 v;
       v.x = x[e]; v.y = x[e + 1]; v.z = x[e + 2]; v.w = x[e + 3];
-      g.st4(idxL<G>(e, t), v);
+      g.put4(b, G::eoff(G::NPASS - 1, e), v);
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) g.st(idxL<G>(e, t), x[e]);
+    for (int e = 0; e < G::E; ++e) g.put(b, G::eoff(G::NPASS - 1, e), x[e]);
   }
 }
 
+// lazy accumulate: a, v in [0, 2q) -> [0, 2q)
+__device__ __forceinline__ uint32_t acc2(uint32_t a, uint32_t v, uint32_t q) {
+  const uint32_t s = a + v;
+  return umin(s, s - 2 * q);
+}
+
 // four residues e .. e + 3 (e a multiple of 4) of the last-pass layout at
-// base + index: one vector load when the last pass keeps chunks of at least 4
-// contiguous residues, else four loads (a last pass of 1 stage keeps pairs)
+// sbase + index (b: the thread's last-pass base): one vector load when the last
+// pass keeps chunks of at least 4 contiguous residues, else four loads (a last
+// pass of 1 stage keeps pairs)
 template <class G>
-__device__ __forceinline__ u32x4 ld4L(const DBuf& g, uint32_t base, int e) {
+__device__ __forceinline__ u32x4 ld4L(const DBuf& g, uint32_t b, uint32_t sbase, int e) {
   constexpr int C = 1 << G::r(G::NPASS - 1);
+  constexpr int PL = G::NPASS - 1;
   if constexpr (C % 4 == 0) {
-    return g.ld4(base + idxLf<G>(e));
+    return g.at4(b, sbase + G::eoff(PL, e));
   } else {
     u32x4 v;
-    v.x = g[base + idxLf<G>(e)];
-    v.y = g[base + idxLf<G>(e + 1)];
-    v.z = g[base + idxLf<G>(e + 2)];
-    v.w = g[base + idxLf<G>(e + 3)];
+    v.x = g.at(b, sbase + G::eoff(PL, e));
+    v.y = g.at(b, sbase + G::eoff(PL, e + 1));
+    v.z = g.at(b, sbase + G::eoff(PL, e + 2));
+    v.w = g.at(b, sbase + G::eoff(PL, e + 3));
     return v;
   }
 }
@@ -217,11 +241,6 @@ __device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r1) {
   return (uint64_t)(uint32_t)(x >> 32) * r1 + (uint32_t)x;
 }
 
-// lazy accumulate: a, v in [0, 2q) -> [0, 2q)
-__device__ __forceinline__ uint32_t acc2(uint32_t a, uint32_t v, uint32_t q) {
-  const uint32_t s = a + v;
-  return umin(s, s - 2 * q);
-}
 
 // ------------------------------------------------------------------ batched transform
 template <int LOGN, bool INV>
@@ -453,11 +472,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
   const size_t lp = blockIdx.x / c.L;
   const int i = blockIdx.x % c.L;
   const DBuf src(cin + (lp * 2 * c.L + c.L + i) * G::N, G::N);
+  uint32_t* wr = lds + G::pad((uint32_t)t);
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) {
-    const uint32_t k = idx0<G>(e, t);
-    lds[G::pad(k)] = src[k];
-  }
+  for (int e = 0; e < G::E; ++e) wr[G::padoff(G::eoff(0, e))] = src.at((uint32_t)t, G::eoff(0, e));
   __syncthreads();
   uint32_t x[G::E];
 #pragma unroll
@@ -523,8 +540,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   if constexpr (DP) {
     const int first = r == 0 ? 1 : 0;
     if (first < L) {
+      const uint32_t tb = (uint32_t)tid_fresh();
 #pragma unroll
-      for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)first * G::N + idx0f<G>(e)];
+      for (int e = 0; e < G::E; ++e) xn[e] = dp.at(tb, (uint32_t)first * G::N + G::eoff(0, e));
     }
   }
   for (int i = 0; i < L; ++i) {
@@ -542,20 +560,23 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
         int nx = i + 1;
         if (nx == r) ++nx;
         if (nx < L) {
+          const uint32_t tb = (uint32_t)tid_fresh();
 #pragma unroll
-          for (int e = 0; e < G::E; ++e) xn[e] = dp[(uint32_t)nx * G::N + idx0f<G>(e)];
+          for (int e = 0; e < G::E; ++e) xn[e] = dp.at(tb, (uint32_t)nx * G::N + G::eoff(0, e));
         }
       } else {
+        const uint32_t tb = (uint32_t)tid_fresh();
 #pragma unroll
-        for (int e = 0; e < G::E; ++e) x[e] = dp[(uint32_t)i * G::N + idx0f<G>(e)];
+        for (int e = 0; e < G::E; ++e) x[e] = dp.at(tb, (uint32_t)i * G::N + G::eoff(0, e));
       }
       ntt_fwd<G, DB, PF>(x, lds, tw, mr, tid_fresh(), &par);
     }
     // keep the key loads below the transform: hoisting them into it costs 64 VGPRs
     __builtin_amdgcn_sched_barrier(0);
+    const uint32_t bL = G::tbase(G::NPASS - 1, tid_fresh());
 #pragma unroll
     for (int e = 0; e < G::E; e += 4) {
-      const u32x4 vb = ld4L<G>(kr, kb, e), va = ld4L<G>(kr, ka, e);
+      const u32x4 vb = ld4L<G>(kr, bL, kb, e), va = ld4L<G>(kr, bL, ka, e);
       if constexpr (A64) {
         // x < q_r and key words < q_r: each product < 2^60
         ab64[e] += (uint64_t)x[e] * vb.x;
@@ -646,20 +667,23 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
   const uint32_t hq = c.hmod[j], pinv = c.pinv_m[j];
   // b part: rho - h + q_j < P + q_j < 4 q_j is a valid lazy input
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = rho[idx0<G>(e, t)] + md.q - hq;
+  for (int e = 0; e < G::E; ++e) x[e] = rho.at((uint32_t)t, G::eoff(0, e)) + md.q - hq;
   ntt_fwd<G>(x, lds, tw, md, t);
   uint32_t a[G::E];
   loadL<G>(acc, a, t);
+  uint32_t cz[G::E];
+  loadL<G>(c0, cz, t);
+  const uint32_t bL = G::tbase(G::NPASS - 1, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
-    const uint32_t k = idxL<G>(e, t);
+    const uint32_t k = bL + G::eoff(G::NPASS - 1, e);
     const uint32_t ob = red1(mulm(a[e] + md.q - x[e], pinv, md.q, md.qinv), md.q);
-    x[e] = addm(addm(c0[k], c0[auto_perm(k, g, LOGN)], md.q), ob, md.q);
+    x[e] = addm(addm(cz[e], c0[auto_perm(k, g, LOGN)], md.q), ob, md.q);
   }
   storeL<G>(DBuf(cout + (lp * 2 * L + j) * G::N, G::N), x, t);
   // a part
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = rho[G::N + idx0<G>(e, t)] + md.q - hq;
+  for (int e = 0; e < G::E; ++e) x[e] = rho.at((uint32_t)t, G::N + G::eoff(0, e)) + md.q - hq;
   ntt_fwd<G>(x, lds, tw, md, t);
   const DBuf acca(ACC + (lp * (L + 1) + j) * 2 * G::N + G::N, G::N);
   loadL<G>(acca, a, t);

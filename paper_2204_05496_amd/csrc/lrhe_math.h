@@ -97,6 +97,20 @@ struct Geom {
   }
   // padded position in the exchange buffer
   LRHE_HD static uint32_t pad(uint32_t j) { return j + (j >> PADSH); }
+  // idx(p, t, e) = tbase(p, t) + eoff(p, e), the two parts on disjoint bits
+  // (h field, stride field, low field; T is a multiple of the stride), so also
+  // pad(idx) = pad(tbase) + padoff(eoff): one per-thread base and a
+  // compile-time offset per element.
+  LRHE_HD static uint32_t tbase(int p, int t) {
+    const int ls = LOGN - s0(p) - r(p);
+    const uint32_t ut = (uint32_t)t;
+    return ((ut >> ls) << (LOGN - s0(p))) + (ut & ((1u << ls) - 1));
+  }
+  LRHE_HD static constexpr uint32_t eoff(int p, int e) {
+    return ((((uint32_t)(e >> r(p)) * (uint32_t)T) >> (LOGN - s0(p) - r(p))) << (LOGN - s0(p))) +
+           (((uint32_t)e & ((1u << r(p)) - 1)) << (LOGN - s0(p) - r(p)));
+  }
+  LRHE_HD static constexpr uint32_t padoff(uint32_t o) { return o + (o >> PADSH); }
 };
 
 // Twiddle access: on the host a plain pointer; in the kernels a view with a

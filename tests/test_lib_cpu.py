@@ -136,3 +136,15 @@ def test_host_decrypt_matches_oracle(P, pname):
     zo, bo = o.decrypt_slots(ko, ct)
     assert np.array_equal(slots[0], zo) and np.array_equal(slots[0], o.centre(z))
     assert abs(bud[0] - bo) < 1e-6
+
+
+def test_geometry_index_split(tmp_path):
+    """The kernels address every element as a per-thread base plus a per-element
+    constant; the split must reproduce the transform's index map exactly."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "geom_check")
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-I", os.path.join(root, "paper_2204_05496_amd", "csrc"),
+                           os.path.join(root, "tests", "geom_check.cpp"), "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout
