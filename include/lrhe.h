@@ -232,7 +232,9 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * classes, for tiles of fewer than "small_below" pairs (default 1024; such
  * launches are latency-bound) and for larger tiles: "small.<key>" and
  * "large.<key>" address one class, a bare key sets both and reads the large
- * class.  Defaults: large 5/5/5/5 and mac_mode 0, small 5/5/5/5 and mac_mode 3.
+ * class.  Defaults: large tiles le_intt 5, le_mac 6, le_moddown 6, le_mask 4
+ * (each 5 where the ring dimension does not allow it) and mac_mode 1; small
+ * tiles 5/5/5/5 and mac_mode 3.
  * "tile" = pairs per tile (default 4096; the workspace size depends on it).
  * No choice changes any result bit.  EINVAL for unknown keys or unavailable
  * values. */

@@ -204,6 +204,8 @@ static void host_ntt_passes(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse
 }
 
 // ------------------------------------------------------------------ context
+static bool le_valid(uint32_t logn, int le);
+
 extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out) {
   if (!p || !out) return fail(LRHE_EINVAL, "null argument");
   *out = nullptr;
@@ -246,6 +248,14 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
   for (uint32_t s = n / 4; s >= 1; s /= 2) c->gal.push_back((uint32_t)powmod64(3, s, 2 * n));
   c->gal.push_back(2 * n - 1);
   c->ngal = (uint32_t)c->gal.size();
+  // default launch choices for large tiles, as measured on 512 x 40,000 at
+  // n = 16384 (64 residues per thread for the inner-product and mod-down
+  // kernels, 16 for the mask, where the ring dimension allows them)
+  c->tune.large.le_intt = 5;
+  c->tune.large.le_mac = le_valid(c->logn, 6) ? 6 : 5;
+  c->tune.large.le_moddown = le_valid(c->logn, 6) ? 6 : 5;
+  c->tune.large.le_mask = le_valid(c->logn, 4) ? 4 : 5;
+  c->tune.large.mac_mode = 1;
   // moduli and twiddle tables (data primes, P, t)
   std::vector<uint32_t> all = qs;
   all.push_back(p->t);
