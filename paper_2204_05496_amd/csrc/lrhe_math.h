@@ -129,8 +129,11 @@ LRHE_HD void stage_tw(int p, int t, int u, int tau, const TW& tw, uint32_t* w) {
   const int rr = G::r(p), sh = G::s0(p);
   const int lstride = G::LOGN - sh - rr;
   const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
+  // a fixed trip count, so the loop unrolls before tau is known; the guards
+  // fold once the callers' stage loops are unrolled
 #pragma unroll
-  for (int j = 0; j < (1 << tau); ++j) w[j] = tw_get(tw, (uint32_t)((1 << (sh + tau)) + (h << tau) + j), sh == 0);
+  for (int j = 0; j < (G::E > 1 ? G::E / 2 : 1); ++j)
+    if (j < (1 << tau)) w[j] = tw_get(tw, (uint32_t)((1 << (sh + tau)) + (h << tau) + j), sh == 0);
 }
 
 // One pass of the forward (Cooley-Tukey) transform on the E registers of

@@ -83,7 +83,7 @@ def test_every_tuning_choice_same_bits(P, torch, pname, rows, f, classes):
         assert np.array_equal(to_numpy_u32(ctx.to_coeff(ref)).astype(np.uint64), exp)
     les = valid_les(ctx)
     say(pname, "valid residues-per-thread", les)
-    for le, mode in itertools.product(les, range(4)):
+    for le, mode in itertools.product(les, range(P.native.MAC_MODES)):
         for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
             ctx.tune_set(knob, le)
         ctx.tune_set("mac_mode", mode)
@@ -114,7 +114,7 @@ def test_autotuner_keeps_bits(P, torch):
     say("autotuned", tuned)
     for cls in ("small", "large"):
         t = tuned[cls]
-        assert t["mac_mode"] in range(4) and all(t[k] in (4, 5, 6) for k in ("le_intt", "le_mac", "le_moddown"))
+        assert t["mac_mode"] in range(P.native.MAC_MODES) and all(t[k] in (4, 5, 6) for k in ("le_intt", "le_mac", "le_moddown"))
     y = ctx.matmul_fast(keys, model, xct, wl.rows)
     torch.cuda.synchronize()
     assert torch.equal(y, ref)
