@@ -308,7 +308,7 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = rows * args.steps / dt
     kern = {}
-    for name in ("k_ks_mac", "k_ks_intt", "k_ks_moddown", "k_mac", "k_mask", "k_compress", "k_encrypt", "k_encode",
+    for name in ("k_ks_mac", "k_ks_intt", "k_ks_rho", "k_ks_moddown", "k_mac", "k_mask", "k_compress", "k_encrypt", "k_encode",
                  "k_sample"):
         c, ms = prof_get(lib, name)
         kern[name] = {"launches": c, "avg_ms": ms / c if c else None, "total_ms_per_step": ms / args.steps}

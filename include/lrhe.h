@@ -228,14 +228,19 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * one LDS exchange buffer and two workgroups per CU, the workgroups of a pair
  * on one XCD; 1: as 0 with the twiddles of the next butterfly stage loaded
  * ahead; 2: double-buffered exchange, pair per XCD, unreduced 64-bit inner
- * products; 3: double-buffered exchange with the next digit loaded ahead.  These five keys exist in two
- * classes, for tiles of fewer than "small_below" pairs (default 1024; such
- * launches are latency-bound) and for larger tiles: "small.<key>" and
- * "large.<key>" address one class, a bare key sets both and reads the large
- * class.  Defaults: large tiles le_intt 5, le_mac 6, le_moddown 6, le_mask 4
- * (each 5 where the ring dimension does not allow it) and mac_mode 1; small
- * tiles 5/5/5/5 and mac_mode 3.
- * "tile" = pairs per tile (default 4096; the workspace size depends on it).
+ * products; 3: double-buffered exchange with the next digit loaded ahead;
+ * 4: as 2 with the digits of each (pair, modulus) item split over two
+ * workgroups, the special-prime inverse transforms in a kernel of their own
+ * and the division by P split by ciphertext part (more workgroups for tiles
+ * too small to fill the GPU; small class only, EINVAL for the large class or
+ * a bare key).  These five keys exist in two classes, for tiles of fewer than
+ * "small_below" pairs (default 1024; such launches are latency-bound) and for
+ * larger tiles: "small.<key>" and "large.<key>" address one class, a bare key
+ * sets both and reads the large class.  Defaults: large tiles le_intt 5,
+ * le_mac 6, le_moddown 6, le_mask 4 (each 5 where the ring dimension does not
+ * allow it) and mac_mode 1; small tiles 5/5/5/5 and mac_mode 3.
+ * "tile" = pairs per tile (default 4096), "small_below" as above; the
+ * workspace size depends on both (small tiles hold two accumulators per pair).
  * No choice changes any result bit.  EINVAL for unknown keys or unavailable
  * values. */
 int lrhe_tune_set(lrhe_ctx* ctx, const char* key, int value);

@@ -982,6 +982,9 @@ extern "C" int lrhe_tune_set(lrhe_ctx* c, const char* key, int value) {
   if (!f) return fail(LRHE_EINVAL, "unknown tuning key '%s'", key);
   if (k == "mac_mode") {
     if (value < 0 || value >= LRHE_MAC_NMODES) return fail(LRHE_EINVAL, "mac_mode must be in [0, %d)", LRHE_MAC_NMODES);
+    if (value == LRHE_MAC_MODE_HALF && kn != &c->tune.small)
+      return fail(LRHE_EINVAL, "mac_mode %d is a choice of the small-tile class only (small.mac_mode)",
+                  LRHE_MAC_MODE_HALF);
   } else if (!le_valid(c->logn, value)) {
     return fail(LRHE_EINVAL, "%s = %d not available at n = %u", key, value, c->n);
   }
@@ -1011,10 +1014,18 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   // the class of this job's tiles is the one tuned
   const uint64_t npairs = (uint64_t)rows * m->classes;
   lrhe::Knobs& K = c->tune.knobs(std::min<uint64_t>(npairs, c->tune.tile));
-  const char* names[4] = {"k_ks_intt", "k_ks_moddown", "k_mask", "k_ks_mac"};
+  const char* names[5] = {"k_ks_intt", "k_ks_moddown", "k_mask", "k_ks_mac", "k_ks_rho"};
   int* knobs[3] = {&K.le_intt, &K.le_moddown, &K.le_mask};
-  double best_ms[3] = {1e300, 1e300, 1e300}, best_mac = 1e300;
-  int best_le[3] = {K.le_intt, K.le_moddown, K.le_mask}, best_mac_le = K.le_mac, best_mode = K.mac_mode;
+  double best_ms[3] = {1e300, 1e300, 1e300};
+  int best_le[3] = {K.le_intt, K.le_moddown, K.le_mask};
+  // per (residues per thread, variant): k_ks_mac time, and for the digit-halves
+  // variant the whole of its step after k_ks_intt (k_ks_mac + k_ks_rho + its
+  // k_ks_moddown), which the others are compared against with their best k_ks_moddown
+  const bool small_class = &K == &c->tune.small;
+  double mac_ms[3][LRHE_MAC_NMODES], half_ms[3];
+  for (auto& row : mac_ms)
+    for (double& v : row) v = 1e300;
+  for (double& v : half_ms) v = 1e300;
   auto timed = [&](double* ms_out, int nk) -> int {
     int rc = lrhe_matmul_fast(c, gk, m, xct, rows, y_out, ws, ws_bytes, stream);   // warm-up
     if (rc != LRHE_OK) return rc;
@@ -1040,9 +1051,10 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
     if (!le_valid(c->logn, le)) continue;
     K.le_intt = K.le_moddown = K.le_mask = K.le_mac = le;
     for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
+      if (mode == LRHE_MAC_MODE_HALF && !small_class) continue;
       K.mac_mode = mode;
-      double ms[4];
-      const int rc = timed(ms, 4);
+      double ms[5];
+      const int rc = timed(ms, 5);
       if (rc != LRHE_OK) return rc;
       if (mode == 0) {
         for (int k = 0; k < 3; ++k)
@@ -1051,14 +1063,25 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
             best_le[k] = le;
           }
       }
-      if (ms[3] < best_mac) {
-        best_mac = ms[3];
+      mac_ms[le - 4][mode] = ms[3];
+      if (mode == LRHE_MAC_MODE_HALF) half_ms[le - 4] = ms[3] + ms[4] + ms[1];
+    }
+  }
+  for (int k = 0; k < 3; ++k) *knobs[k] = best_le[k];
+  double best = 1e300;
+  int best_mac_le = K.le_mac, best_mode = 0;
+  for (int le = 4; le <= 6; ++le)
+    for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
+      const double cost = mode == LRHE_MAC_MODE_HALF ? half_ms[le - 4] : mac_ms[le - 4][mode] + best_ms[1];
+      if (cost < best) {
+        best = cost;
         best_mac_le = le;
         best_mode = mode;
       }
     }
-  }
-  for (int k = 0; k < 3; ++k) *knobs[k] = best_le[k];
+  // the digit-halves variant runs its own k_ks_rho and k_ks_moddown at the
+  // residues per thread it was timed with
+  if (best_mode == LRHE_MAC_MODE_HALF) K.le_moddown = best_mac_le;
   K.le_mac = best_mac_le;
   K.mac_mode = best_mode;
   return LRHE_OK;

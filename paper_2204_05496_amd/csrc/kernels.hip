@@ -104,7 +104,8 @@ FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes) {
   w.cA = off; off += al(B * ctb);
   w.cB = off; off += al(B * ctb);
   w.D = off; off += al(B * L * n * 4);
-  w.ACC = off; off += al(B * (L + 1) * 2 * n * 4);
+  w.acc_slots = acc_slots(c, B);
+  w.ACC = off; off += al(w.acc_slots * (L + 1) * 2 * n * 4);
   w.part = off; off += al(ngroups * ctb);
   w.desc = off; off += al(npairs * sizeof(PairDesc)) + al(ngroups * sizeof(GroupDesc)) + al(nouts * sizeof(OutDesc));
   w.total = off;
@@ -114,7 +115,7 @@ FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes) {
 hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* pairs, uint32_t npairs,
                        const GroupDesc* groups, const uint32_t* tile_g0, uint32_t B, const OutDesc* outs,
                        uint32_t nouts, int stage, uint32_t* out, uint32_t* cA, uint32_t* cB, uint32_t* D,
-                       uint32_t* ACC, uint32_t* part, hipStream_t s) {
+                       uint32_t* ACC, uint64_t acc_slots, uint32_t* part, hipStream_t s) {
   const uint64_t n = c->n, L = c->L;
   const uint64_t ctw = 2 * L * n;
   for (uint32_t t = 0, pb = 0; pb < npairs; ++t, pb += B) {
@@ -136,7 +137,7 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
     const int steps = (stage >= 2 && stage < 100) ? stage - 2 : (int)c->ngal;
     for (int gi = 0; gi < steps; ++gi) {
       hipError_t e = hipErrorInvalidValue;
-      LRHE_DISPATCH(c->logn, e = launch_ks_step<LN>(c, kn, tp, gk_d, Bt, (uint32_t)gi, cur, D, ACC, nxt, s));
+      LRHE_DISPATCH(c->logn, e = launch_ks_step<LN>(c, kn, tp, gk_d, Bt, (uint32_t)gi, cur, D, ACC, acc_slots, nxt, s));
       if (e != hipSuccess) return e;
       uint32_t* tmp = cur;
       cur = nxt;
@@ -179,7 +180,7 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
   tile_g0.push_back(ngroups);
   return launch_plan(c, gk_d, pairs, npairs, groups, tile_g0.data(), lay.B, outs, nouts, stage, out,
                      (uint32_t*)(base + lay.cA), (uint32_t*)(base + lay.cB), (uint32_t*)(base + lay.D),
-                     (uint32_t*)(base + lay.ACC), (uint32_t*)(base + lay.part), s);
+                     (uint32_t*)(base + lay.ACC), lay.acc_slots, (uint32_t*)(base + lay.part), s);
 }
 
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,

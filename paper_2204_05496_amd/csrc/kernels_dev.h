@@ -491,13 +491,16 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // LDS; 2 = the next digit is loaded during the current transform; 4 = the
 // twiddles of the next butterfly stage are loaded during the current one;
 // 8 = a register cap that lets two workgroups share a CU (only useful
-// single-buffered); 128 = the inner products accumulate unreduced 64-bit
-// products (one multiply-add each, folded every 4 digits) instead of reducing
-// every product.
+// single-buffered); 32 and 64 = workgroup order (below); 128 = the inner
+// products accumulate unreduced 64-bit products (one multiply-add each, folded
+// every 4 digits) instead of reducing every product; 256 = two workgroups per
+// item, one for each half of the digits, writing their sums to ACC and ACC2
+// (canonical, no inverse transform for r = P; k_ks_rho finishes that item).
 template <int LOGN, int LE, int MODE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
     DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
-    const uint32_t* __restrict__ gk_default, uint32_t gi, uint32_t g, uint32_t* __restrict__ ACC) {
+    const uint32_t* __restrict__ gk_default, uint32_t gi, uint32_t g, uint32_t* __restrict__ ACC,
+    uint32_t* __restrict__ ACC2) {
   using G = Geom<LOGN, LE>;
   constexpr bool DB = (MODE & 1) && 2 * G::LDS_WORDS * 4 <= 160 * 1024;
   constexpr bool DP = (MODE & 2) != 0;   // digit prefetch
@@ -513,12 +516,19 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   if constexpr ((MODE & 64) != 0) {
     if (gridDim.x % 8 == 0) li = (li % 8) * (gridDim.x / 8) + li / 8;
   }
-  const size_t lp = li / (L + 1);
-  // the special-prime item (r = L) carries more work than the others, so its
-  // XCD is rotated per pair (MODE 16: between two XCDs, MODE 32: over all)
-  int r = (int)(li % (L + 1));
-  if constexpr ((MODE & 16) != 0) r = (r + ((L + 1) / 2) * (int)(lp & 1)) % (L + 1);
+  constexpr bool HALF = (MODE & 256) != 0;
+  const int per_pair = HALF ? 2 * (L + 1) : L + 1;   // workgroups per pair
+  const size_t lp = li / per_pair;
+  const int wi = (int)(li % per_pair);
+  // the special-prime item (r = L) carries more work than the others; MODE 32
+  // rotates its place among the pair's workgroups from pair to pair, so the
+  // heavy items spread over the launch order
+  int r = HALF ? wi >> 1 : wi;
   if constexpr ((MODE & 32) != 0) r = (r + (int)(lp % (L + 1))) % (L + 1);
+  // digits of this workgroup: all of them, or one half
+  const int half = HALF ? wi & 1 : 0;
+  const int i_lo = half ? (L + 1) / 2 : 0;
+  const int i_hi = HALF && !half ? (L + 1) / 2 : L;
   const Mod mr = c.mod[r];
   const TwView tw = twv(c.tw, r, G::N);
   // the pair's Galois key for element gi, target modulus r: [L digits][2][n]
@@ -538,14 +548,14 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   // prefetched into xn while the current transform runs
   [[maybe_unused]] uint32_t xn[DP ? G::E : 1];
   if constexpr (DP) {
-    const int first = r == 0 ? 1 : 0;
-    if (first < L) {
+    const int first = r == i_lo ? i_lo + 1 : i_lo;
+    if (first < i_hi) {
       const uint32_t tb = (uint32_t)tid_fresh();
 #pragma unroll
       for (int e = 0; e < G::E; ++e) xn[e] = dp.at(tb, (uint32_t)first * G::N + G::eoff(0, e));
     }
   }
-  for (int i = 0; i < L; ++i) {
+  for (int i = i_lo; i < i_hi; ++i) {
     const uint32_t kb = (uint32_t)(2 * i) * G::N, ka = kb + G::N;
     if (i == r) {
       // [d_r]_{q_r} in evaluation form is limb r of sigma_g(c1): a permutation of the input
@@ -559,7 +569,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
         for (int e = 0; e < G::E; ++e) x[e] = xn[e];
         int nx = i + 1;
         if (nx == r) ++nx;
-        if (nx < L) {
+        if (nx < i_hi) {
           const uint32_t tb = (uint32_t)tid_fresh();
 #pragma unroll
           for (int e = 0; e < G::E; ++e) xn[e] = dp.at(tb, (uint32_t)nx * G::N + G::eoff(0, e));
@@ -618,9 +628,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
     }
   }
   const int t = tid_fresh();
-  uint32_t* out = ACC + (lp * (L + 1) + r) * 2 * G::N;
+  uint32_t* out = (half ? ACC2 : ACC) + (lp * (L + 1) + r) * 2 * G::N;
   const DBuf ob(out, G::N), oa(out + G::N, G::N);
-  if (r < L) {
+  if (HALF || r < L) {
 #pragma unroll
     for (int e = 0; e < G::E; ++e) { ab[e] = red1(ab[e], mr.q); aa[e] = red1(aa[e], mr.q); }
     storeL<G>(ob, ab, t);
@@ -637,6 +647,76 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
     for (int e = 0; e < G::E; ++e) aa[e] = addm(aa[e], h, mr.q);
     store0<G>(oa, aa, t);
   }
+}
+
+// key switch, small-tile variant, between parts 2 and 3: the special-prime
+// sums of the two digit halves, acc_x = ACC + ACC2, become rho_x =
+// [INTT(acc_x) + (P-1)/2]_P, written over ACC.  One workgroup per (pair, x).
+template <int LOGN, int LE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_rho(DevCtx c, uint32_t* __restrict__ ACC,
+                                                               const uint32_t* __restrict__ ACC2) {
+  using G = Geom<LOGN, LE>;
+  const int t = threadIdx.x;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const int L = c.L;
+  const size_t lp = blockIdx.x >> 1;
+  const size_t off = (lp * (L + 1) + L) * 2 * G::N + (blockIdx.x & 1) * G::N;
+  const Mod mp = c.mod[L];
+  uint32_t x[G::E], y[G::E];
+  loadL<G>(DBuf(ACC + off, G::N), x, t);
+  loadL<G>(DBuf(ACC2 + off, G::N), y, t);
+  // both below P: the sum is below 2P, a valid inverse-transform input.  Every
+  // load is consumed before the first exchange barrier, so the in-place store
+  // below cannot overtake another thread's load.
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] += y[e];
+  ntt_inv<G>(x, lds, twv(c.itw, L, G::N), mp, t);
+  const uint32_t h = (mp.q - 1) / 2;
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = addm(x[e], h, mp.q);
+  store0<G>(DBuf(ACC + off, G::N), x, t);
+}
+
+// key switch, part 3 of the small-tile variant: k_ks_moddown for one output
+// limb and one part x (b or a) per workgroup, the accumulator being ACC + ACC2
+template <int LOGN, int LE>
+__global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown_part(DevCtx c, const uint32_t* __restrict__ cin,
+                                                                        const uint32_t* __restrict__ ACC,
+                                                                        const uint32_t* __restrict__ ACC2, uint32_t g,
+                                                                        uint32_t* __restrict__ cout) {
+  using G = Geom<LOGN, LE>;
+  const int t = threadIdx.x;
+  __shared__ uint32_t lds[G::LDS_WORDS];
+  const int L = c.L;
+  const size_t lp = blockIdx.x / (2 * L);
+  const int j = (int)(blockIdx.x % (2 * L)) >> 1;
+  const uint32_t part = blockIdx.x & 1;
+  const Mod md = c.mod[j];
+  const uint32_t hq = c.hmod[j], pinv = c.pinv_m[j];
+  const size_t slot = (lp * (L + 1) + j) * 2 * G::N + part * G::N;
+  const DBuf rho(ACC + (lp * (L + 1) + L) * 2 * G::N + part * G::N, G::N);
+  uint32_t x[G::E];
+  // rho - h + q_j < P + q_j < 4 q_j is a valid lazy input
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) x[e] = rho.at((uint32_t)t, G::eoff(0, e)) + md.q - hq;
+  ntt_fwd<G>(x, lds, twv(c.tw, j, G::N), md, t);
+  uint32_t a[G::E], a2[G::E];
+  loadL<G>(DBuf(ACC + slot, G::N), a, t);
+  loadL<G>(DBuf(ACC2 + slot, G::N), a2, t);
+  const DBuf cj(cin + (lp * 2 * L + part * L + j) * G::N, G::N);
+  uint32_t cz[G::E];
+  loadL<G>(cj, cz, t);
+  const uint32_t bL = G::tbase(G::NPASS - 1, t);
+#pragma unroll
+  for (int e = 0; e < G::E; ++e) {
+    const uint32_t acc = addm(a[e], a2[e], md.q);
+    const uint32_t o = red1(mulm(acc + md.q - x[e], pinv, md.q, md.qinv), md.q);
+    // b part: c0 + sigma_g(c0) + out_b; a part: c1 + out_a
+    uint32_t v = cz[e];
+    if (part == 0) v = addm(v, cj[auto_perm(bL + G::eoff(G::NPASS - 1, e), g, LOGN)], md.q);
+    x[e] = addm(v, o, md.q);
+  }
+  storeL<G>(DBuf(cout + (lp * 2 * L + part * L + j) * G::N, G::N), x, t);
 }
 
 // key switch, part 3: rounded division by P, coefficient-wise

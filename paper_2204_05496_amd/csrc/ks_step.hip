@@ -26,18 +26,28 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
 // k_ks_mac variants selectable through the "mac_mode" tuning key (index -> MODE bits)
 #ifndef LRHE_MAC_MODES
 #define LRHE_MAC_MODE_CASE(IDX, LN, LE, MODE) \
-  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC); break;
+  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC, ACC2); break;
 #define LRHE_MAC_MODES(LN, LE)                                                           \
   LRHE_MAC_MODE_CASE(0, LN, LE, 104) /* one buffer, 2 workgroups/CU, pair per XCD, rotated */ \
   LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
   LRHE_MAC_MODE_CASE(2, LN, LE, 225) /* double buffer, pair per XCD, rotated, 64-bit MAC */   \
-  LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */
+  LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */                           \
+  LRHE_MAC_MODE_CASE(4, LN, LE, 481) /* as 2, two workgroups per item (digit halves); small tiles */
 #endif
 
 template <int LN>
 hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp, const uint32_t* gk_d, uint32_t Bt,
-                          uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint32_t* nxt, hipStream_t s) {
+                          uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint64_t acc_slots,
+                          uint32_t* nxt, hipStream_t s) {
   const uint32_t L = c->L, g = c->gal[gi];
+  // the digit-halves variant keeps a second accumulator per item, ACC2, in the
+  // slots after the tile's own
+  const bool half = kn.mac_mode == LRHE_MAC_MODE_HALF;
+  uint32_t* ACC2 = nullptr;
+  if (half) {
+    if (2ull * Bt > acc_slots) return hipErrorInvalidValue;
+    ACC2 = ACC + (uint64_t)Bt * (L + 1) * 2 * c->n;
+  }
   {
     ProfScope ps(s, "k_ks_intt");
     LRHE_LE_SWITCH(kn.le_intt, {
@@ -47,14 +57,25 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
   {
     ProfScope ps(s, "k_ks_mac");
     LRHE_LE_SWITCH(kn.le_mac, {
-      const unsigned grid = (unsigned)(Bt * (L + 1));
+      const unsigned grid = (unsigned)(Bt * (L + 1) * (half ? 2 : 1));
       switch (kn.mac_mode) {
         LRHE_MAC_MODES(LN, LE)
         default: return hipErrorInvalidValue;
       }
     });
   }
-  {
+  if (half) {
+    {
+      ProfScope ps(s, "k_ks_rho");
+      LRHE_LE_SWITCH(kn.le_moddown, {
+        k_ks_rho<LN, LE><<<(unsigned)(Bt * 2), Geom<LN, LE>::T, 0, s>>>(c->dc, ACC, ACC2);
+      });
+    }
+    ProfScope ps(s, "k_ks_moddown");
+    LRHE_LE_SWITCH(kn.le_moddown, {
+      k_ks_moddown_part<LN, LE><<<(unsigned)(Bt * L * 2), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, ACC2, g, nxt);
+    });
+  } else {
     ProfScope ps(s, "k_ks_moddown");
     LRHE_LE_SWITCH(kn.le_moddown, {
       k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt);
@@ -74,8 +95,8 @@ hipError_t launch_mask_step(const lrhe_ctx* c, const Knobs& kn, const uint32_t* 
 }
 
 template hipError_t launch_ks_step<LRHE_KS_LOGN>(const lrhe_ctx*, const Knobs&, const PairDesc*, const uint32_t*,
-                                                 uint32_t, uint32_t, const uint32_t*, uint32_t*, uint32_t*, uint32_t*,
-                                                 hipStream_t);
+                                                 uint32_t, uint32_t, const uint32_t*, uint32_t*, uint32_t*, uint64_t,
+                                                 uint32_t*, hipStream_t);
 template hipError_t launch_mask_step<LRHE_KS_LOGN>(const lrhe_ctx*, const Knobs&, const uint32_t*, const PairDesc*,
                                                    const GroupDesc*, uint32_t, int, uint32_t*, hipStream_t);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,7 @@ inline uint32_t std_class_pad(uint32_t classes) { return (classes + 15) / 16 * 1
 
 struct FastWs {
   uint32_t B;                 // pairs per tile
+  uint64_t acc_slots;         // pair slots of ACC (see acc_slots)
   uint32_t G;                 // pairs per compression group
   size_t cA, cB, D, ACC, part, desc, total;   // byte offsets, total size
   size_t npart, ndesc_pairs, ndesc_groups, ndesc_outs;
@@ -68,8 +70,12 @@ namespace lrhe {
 // Launch choices of the fast-matmul kernels (set by lrhe_tune_set / lrhe_autotune_fast):
 // log2 of the residues per thread of each transform kernel, pairs per tile.
 #ifndef LRHE_MAC_NMODES
-#define LRHE_MAC_NMODES 4   // k_ks_mac variants behind the "mac_mode" tuning key
+#define LRHE_MAC_NMODES 5   // k_ks_mac variants behind the "mac_mode" tuning key
 #endif
+// the variant that splits each key-switch item's digits over two workgroups
+// (latency of small tiles); it needs two accumulator slots per tile pair, so
+// it is a choice of the small-tile class only
+#define LRHE_MAC_MODE_HALF 4
 // Launch choices of the transform kernels (none changes a result bit).
 struct Knobs {
   int le_intt = 5, le_mac = 5, le_moddown = 5, le_mask = 5;
@@ -159,6 +165,15 @@ hipError_t launch_encrypt(const lrhe_ctx* c, const uint32_t* pk_d, const int64_t
 size_t encrypt_ws_bytes(const lrhe_ctx* c, uint64_t nct);
 hipError_t launch_model_encode(const lrhe_ctx* c, const int64_t* W, uint32_t f, uint32_t classes, uint32_t* wpt,
                                uint32_t* wsc, hipStream_t s);
+// Pair slots of the key-switch accumulator buffer for tiles of at most B pairs:
+// one per pair, two for the tiles of the small class (the digit-halves variant
+// needs ACC and ACC2); a large job's last tile, if small, fits its two slots per
+// pair in the B slots whenever it has at most B/2 pairs, otherwise the buffer
+// grows.
+inline uint64_t acc_slots(const lrhe_ctx* c, uint64_t B) {
+  const uint64_t small_max = c->tune.small_below > 0 ? c->tune.small_below - 1 : 0;
+  return std::max<uint64_t>(B, 2 * std::min<uint64_t>(B, small_max));
+}
 FastWs fast_ws_layout(const lrhe_ctx* c, uint32_t npairs, uint32_t classes);
 hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model* m, const uint32_t* xct,
                        uint32_t rows, uint32_t pair0, uint32_t npairs, int stage, uint32_t* out, void* ws,
@@ -171,14 +186,15 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
 // and the bias + mask + group sums of a tile
 template <int LN>
 hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp, const uint32_t* gk_d, uint32_t Bt,
-                          uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint32_t* nxt, hipStream_t s);
+                          uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint64_t acc_slots,
+                          uint32_t* nxt, hipStream_t s);
 template <int LN>
 hipError_t launch_mask_step(const lrhe_ctx* c, const Knobs& kn, const uint32_t* cur, const PairDesc* tp,
                             const GroupDesc* tg, uint32_t ngt, int mode, uint32_t* dst, hipStream_t s);
 hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* pairs, uint32_t npairs,
                        const GroupDesc* groups, const uint32_t* tile_g0, uint32_t B, const OutDesc* outs,
                        uint32_t nouts, int stage, uint32_t* out, uint32_t* cA, uint32_t* cB, uint32_t* D,
-                       uint32_t* ACC, uint32_t* part, hipStream_t s);
+                       uint32_t* ACC, uint64_t acc_slots, uint32_t* part, hipStream_t s);
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,
                            hipStream_t s);
 }  // namespace lrhe

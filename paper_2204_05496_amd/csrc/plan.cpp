@@ -46,6 +46,7 @@ uint32_t pick_group(uint64_t npairs) {
 
 struct TileWs {   // per-tile buffers of the key-switch pipeline
   size_t cA, cB, D, ACC, total;
+  uint64_t acc_slots;   // pair slots of ACC (see acc_slots)
 };
 TileWs tile_ws(const lrhe_ctx* c, uint32_t B) {
   const uint64_t n = c->n, L = c->L, ctb = 2 * L * n * 4;
@@ -54,7 +55,8 @@ TileWs tile_ws(const lrhe_ctx* c, uint32_t B) {
   w.cA = off; off += al256(B * ctb);
   w.cB = off; off += al256(B * ctb);
   w.D = off; off += al256((uint64_t)B * L * n * 4);
-  w.ACC = off; off += al256((uint64_t)B * (L + 1) * 2 * n * 4);
+  w.acc_slots = acc_slots(c, B);
+  w.ACC = off; off += al256(w.acc_slots * (L + 1) * 2 * n * 4);
   w.total = off;
   return w;
 }
@@ -180,7 +182,7 @@ static hipError_t batch_launch(lrhe_batch* b, const lrhe_gk* gk, void* ws, hipSt
   char* base = (char*)ws;
   return launch_plan(b->c, gk->d, b->d_pairs, b->npairs, b->d_groups, b->tile_g0.data(), b->B, b->d_outs, b->nouts,
                      -1, nullptr, (uint32_t*)(base + b->tw.cA), (uint32_t*)(base + b->tw.cB),
-                     (uint32_t*)(base + b->tw.D), (uint32_t*)(base + b->tw.ACC), (uint32_t*)(base + b->part_off), s);
+                     (uint32_t*)(base + b->tw.D), (uint32_t*)(base + b->tw.ACC), b->tw.acc_slots, (uint32_t*)(base + b->part_off), s);
 }
 
 extern "C" int lrhe_batch_run(lrhe_ctx* c, const lrhe_gk* gk, lrhe_batch* b, void* ws, size_t ws_bytes, void* stream) {
@@ -426,7 +428,7 @@ void run_tick(lrhe_server* sv, int slot) {
     err = launch_plan(c, sv->gk->d, (PairDesc*)d, (uint32_t)pairs.size(), (GroupDesc*)(d + sp), tg, sv->B,
                       (OutDesc*)(d + sp + sg), (uint32_t)outs.size(), -1, nullptr, (uint32_t*)(tb + sv->tw.cA),
                       (uint32_t*)(tb + sv->tw.cB), (uint32_t*)(tb + sv->tw.D), (uint32_t*)(tb + sv->tw.ACC),
-                      sv->d_part, sv->s);
+                      sv->tw.acc_slots, sv->d_part, sv->s);
   if (err == hipSuccess) err = hipEventRecord(sv->slot_ev[slot], sv->s);
   std::lock_guard<std::mutex> lk(sv->mu);
   for (SReq* r : finishing) {

@@ -16,8 +16,10 @@ LIBPATH = os.path.join(HERE, "liblrhe.so")
 
 LRHE_OK, LRHE_EINVAL, LRHE_EPARAM, LRHE_ENOMEM, LRHE_EAGAIN, LRHE_EDEVICE, LRHE_ENOISE = 0, -1, -2, -3, -4, -5, -6
 WS_ENCRYPT_ROWS, WS_ENCRYPT_COLS, WS_MATMUL_FAST, WS_MATMUL_STANDARD = 1, 2, 3, 4
-# variants of the key-switch inner-product kernel behind the "mac_mode" tuning key
-MAC_MODES = 4
+# variants of the key-switch inner-product kernel behind the "mac_mode" tuning key;
+# MAC_MODE_HALF (digit halves on two workgroups per item) is a small-tile choice only
+MAC_MODES = 5
+MAC_MODE_HALF = 4
 
 vp = ctypes.c_void_p
 u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64

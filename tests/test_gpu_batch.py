@@ -130,6 +130,35 @@ def test_server_mix_equals_alone(tiny_setup, P, torch):
     srv.close()
 
 
+def test_batch_and_server_digit_halves(tiny_setup, P, torch):
+    """The small-tile key-switch variant with the digits of each item split over
+    two workgroups, in a planned batch and in the server: every output equals
+    the request run alone with the default choices."""
+    p, ctx, keys, reqs, alone = tiny_setup
+    before = ctx.tuning()["small"]["mac_mode"]
+    ctx.tune_set("small.mac_mode", P.native.MAC_MODE_HALF)
+    try:
+        ys = [ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n)) for wl, _, _ in reqs]
+        b = P.Batch(ctx, keys, [(xct, wl.rows, model, y) for (wl, xct, model), y in zip(reqs, ys)])
+        b.run()
+        torch.cuda.synchronize()
+        for k, y in enumerate(ys):
+            assert np.array_equal(coeff(ctx, y), alone[k]), f"batch request {k}"
+        srv = P.Server(ctx, keys, hbm_budget=2 << 30)
+        ys2, ids = [], []
+        for wl, xct, model in reqs:
+            y = ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n))
+            ys2.append(y)
+            ids.append(srv.submit(model, xct, wl.rows, y))
+        srv.drain()
+        for k, y in enumerate(ys2):
+            assert srv.poll(ids[k])[0]
+            assert np.array_equal(coeff(ctx, y), alone[k]), f"server request {k}"
+        srv.close()
+    finally:
+        ctx.tune_set("small.mac_mode", before)
+
+
 def test_server_admission_by_memory(tiny_setup, P, torch):
     p, ctx, keys, reqs, alone = tiny_setup
     ctb = 2 * ctx.L * ctx.n * 4

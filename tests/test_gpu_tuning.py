@@ -86,7 +86,7 @@ def test_every_tuning_choice_same_bits(P, torch, pname, rows, f, classes):
     for le, mode in itertools.product(les, range(P.native.MAC_MODES)):
         for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
             ctx.tune_set(knob, le)
-        ctx.tune_set("mac_mode", mode)
+        ctx.tune_set("small.mac_mode", mode)   # every tile of these jobs is in the small class
         say(pname, "le", le, "mac_mode", mode)
         y = ctx.matmul_fast(keys, model, xct, rows)
         torch.cuda.synchronize()
@@ -115,6 +115,39 @@ def test_autotuner_keeps_bits(P, torch):
     for cls in ("small", "large"):
         t = tuned[cls]
         assert t["mac_mode"] in range(P.native.MAC_MODES) and all(t[k] in (4, 5, 6) for k in ("le_intt", "le_mac", "le_moddown"))
+    assert tuned["large"]["mac_mode"] != P.native.MAC_MODE_HALF
     y = ctx.matmul_fast(keys, model, xct, wl.rows)
     torch.cuda.synchronize()
     assert torch.equal(y, ref)
+
+
+def test_digit_halves_small_class_only(P, torch):
+    """The digit-halves key-switch variant is a small-tile choice: setting it for
+    the large class is refused; a job whose last tile is small runs that tile
+    with it (two accumulator slots per pair inside the job's buffer) and keeps
+    every bit."""
+    p = WL.PARAMS["tiny3"]   # three data primes: enough noise budget to decrypt
+    ctx = P.Context.from_params(p, device=0)
+    keys = ctx.keygen(808)
+    half = P.native.MAC_MODE_HALF
+    for key in ("mac_mode", "large.mac_mode"):
+        with pytest.raises(P.native.LrheError):
+            ctx.tune_set(key, half)
+    wl = WL.make("halves", "tiny3", 3, 5000, 4, 0.02, WL.BASE_SEED + 31)   # 12 pairs
+    xct = ctx.encrypt_rows(keys, wl.X, seed=46)
+    model = ctx.model(wl.W, wl.b)
+    ref = ctx.matmul_fast(keys, model, xct, wl.rows)
+    torch.cuda.synchronize()
+    # tiles of 8 pairs (large class) then 4 (small class, digit halves)
+    ctx.tune_set("tile", 8)
+    ctx.tune_set("small_below", 5)
+    ctx.tune_set("small.mac_mode", half)
+    for le in valid_les(ctx):
+        ctx.tune_set("small.le_mac", le)
+        ctx.tune_set("small.le_moddown", le)
+        say("mixed tiles, small class digit halves, le", le)
+        y = ctx.matmul_fast(keys, model, xct, wl.rows)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), f"le {le}"
+    S, budget = ctx.scores_fast(keys, y, wl.rows, wl.classes)
+    assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t))
