@@ -57,10 +57,15 @@ def ring(n, t):
 
 # n = 2048 and 8192 have a last transform pass of a single stage at 32 and 64
 # residues per thread respectively
+# one data prime: the second digit half of the digit-halves variant is empty
 @pytest.mark.parametrize("pname,rows,f,classes", [("tiny", 3, 5000, 4), ("n16k", 1, 40000, 16),
-                                                  ("ring2048", 2, 2500, 3), ("ring8192", 1, 9000, 2)])
+                                                  ("ring2048", 2, 2500, 3), ("ring8192", 1, 9000, 2),
+                                                  ("oneprime", 2, 3000, 3)])
 def test_every_tuning_choice_same_bits(P, torch, pname, rows, f, classes):
-    if pname.startswith("ring"):
+    if pname == "oneprime":
+        ps = ntt_primes(4096, 2)
+        p = WL.Params("oneprime", 4096, (ps[0],), ps[1], 65537, insecure=True)
+    elif pname.startswith("ring"):
         n = int(pname[4:])
         p = ring(n, 12289 if n == 2048 else 65537)
     else:
