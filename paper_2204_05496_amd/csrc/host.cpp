@@ -189,6 +189,31 @@ static void host_ntt_plain(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse)
 static void host_ntt(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
   host_ntt_plain(c, mi, a, inverse);
 }
+// the forward transform of host_ntt_plain with the butterflies of each stage
+// shared among the OpenMP threads (one parallel region, a barrier per stage)
+static void host_ntt_fwd_threads(const lrhe_ctx* c, int mi, uint32_t* a) {
+  const uint32_t n = c->n;
+  const Mod& md = c->mods[mi];
+  const uint32_t q = md.q;
+  const uint32_t* tb = c->h_tw.data() + (size_t)mi * n;
+#pragma omp parallel
+  {
+#pragma omp for schedule(static)
+    for (int i = 0; i < (int)n; ++i) a[i] = red2(a[i], q);
+    for (uint32_t m = 1, lh = c->logn - 1; m < n; m <<= 1, --lh) {
+      const uint32_t h = 1u << lh;
+      // butterfly b of the stage: block i = b / h, offset j = b % h
+#pragma omp for schedule(static)
+      for (int b = 0; b < (int)(n / 2); ++b) {
+        const uint32_t i = (uint32_t)b >> lh, j = (uint32_t)b & (h - 1);
+        uint32_t* x = a + (size_t)2 * i * h;
+        const uint32_t u = x[j], v = red1(mulm(x[j + h], tb[m + i], q, md.qinv), q);
+        x[j] = addm(u, v, q);
+        x[j + h] = subm(u, v, q);
+      }
+    }
+  }
+}
 // the pass-structured version: the kernels' own pass arithmetic, emulated
 static void host_ntt_passes(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
   const uint32_t* tb = (inverse ? c->h_itw.data() : c->h_tw.data()) + (size_t)mi * c->n;
@@ -464,6 +489,9 @@ extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk*
   sk->L = L;
   sk->s.assign(s.begin(), s.end());
   sk->S.assign(S.begin(), S.begin() + (size_t)L * n);
+  sk->Sm.resize((size_t)L * n);
+  for (uint32_t j = 0; j < L; ++j)
+    for (uint32_t k = 0; k < n; ++k) sk->Sm[(size_t)j * n + k] = to_mont(sk->S[(size_t)j * n + k], c->mods[j]);
   // public key: pk = (-(a s + e), a) mod Q, evaluation form
   auto* pk = new lrhe_pk();
   pk->h.assign((size_t)2 * L * n, 0);
@@ -650,6 +678,14 @@ struct Fixed {
 inline void fx_from(Fixed& a, const Big& b) {
   for (int i = 0; i < FW; ++i) a.w[i] = i < (int)b.size() ? b[i] : 0;
 }
+inline void fx_add_mul32(Fixed& acc, const Fixed& a, uint32_t m, int nw) {   // acc += a m (nw words)
+  uint64_t carry = 0;
+  for (int i = 0; i < nw; ++i) {   // below (2^32 - 1)^2 + 2 (2^32 - 1) = 2^64 - 1
+    const uint64_t v = (uint64_t)a.w[i] * m + acc.w[i] + carry;
+    acc.w[i] = (uint32_t)v;
+    carry = v >> 32;
+  }
+}
 inline void fx_add_mul(Fixed& acc, const Fixed& a, uint64_t m, int nw) {   // acc += a m (nw words)
   unsigned __int128 carry = 0;
   for (int i = 0; i < nw; ++i) {
@@ -699,6 +735,12 @@ static int decrypt_host(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* h, uint3
   for (uint32_t j = 0; j < L; ++j) fx_from(Qhat[j], c->Qhat[j]);
   // words that hold 2^64 Q: sums of L terms below 2^64 Q, and k0 Q
   const int nw = std::min(FW, (int)((c->log2Q + 66) / 32) + 2);
+  // RQ_j = R_j (Q / q_j), below q_j Q: the terms of N are x_j RQ_j with 32-bit x_j
+  Fixed RQ[LRHE_MAXL];
+  for (uint32_t j = 0; j < L; ++j) {
+    RQ[j] = Fixed{};
+    fx_add_mul32(RQ[j], Qhat[j], c->dec_R[j], nw);
+  }
   int bad = 0;
   // one ciphertext: x_j = [c0 + c1 s]_{q_j} in coefficient form, then
   // m = sum_j x_j I_j + round(sum_j x_j R_j / q_j) mod t with the rounding done
@@ -708,23 +750,33 @@ static int decrypt_host(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* h, uint3
 #pragma omp parallel for schedule(static) if (inner_parallel)
     for (int j = 0; j < (int)L; ++j) {
       const uint64_t q = c->q[j];
-      const uint32_t* Sj = &sk->S[(size_t)j * n];
+      const uint32_t* Sj = &sk->Sm[(size_t)j * n];
+      const Mod& md = c->mods[j];
       uint32_t* xj = &X[(size_t)j * n];
-      for (uint32_t k = 0; k < n; ++k) xj[k] = (uint32_t)((C[(size_t)j * n + k] + (uint64_t)C[(size_t)(L + j) * n + k] * Sj[k]) % q);
+      for (uint32_t k = 0; k < n; ++k) {
+        // c0 + c1 s: the Montgomery product is below 2q, any c0 below 2^32 is
+        // reduced first (a canonical c0 skips the division)
+        const uint32_t c0 = C[(size_t)j * n + k];
+        const uint64_t v = (uint64_t)(c0 < q ? c0 : c0 % q) + mulm(C[(size_t)(L + j) * n + k], Sj[k], (uint32_t)q, md.qinv);
+        xj[k] = (uint32_t)(v >= 2 * q ? v - 2 * q : v >= q ? v - q : v);
+      }
       host_ntt(c, j, xj, true);
     }
     double worst = -INFINITY;
     int err = 0;
 #pragma omp parallel for schedule(static) reduction(max : worst) reduction(| : err) if (inner_parallel)
     for (int k = 0; k < (int)n; ++k) {
+      // sum of x_j I_j mod t: each term below 2^60 (x_j < q_j < 2^30, I_j < t <
+      // 2^30), reduced after every 8 terms so the sum stays below 2^64
       uint64_t mi = 0;
       double approx = 0;
       Fixed N{};
       for (uint32_t j = 0; j < L; ++j) {
         const uint64_t xj = X[(size_t)j * n + k];
-        mi = (mi + xj % t * c->dec_I[j]) % t;
+        mi += xj * c->dec_I[j];
+        if ((j & 7) == 7) mi %= t;
         approx += (double)xj * c->dec_Rf[j];
-        fx_add_mul(N, Qhat[j], xj * c->dec_R[j], nw);
+        fx_add_mul32(N, RQ[j], (uint32_t)xj, nw);
       }
       int64_t k0 = (int64_t)std::floor(approx) - 1;
       if (k0 < 0) k0 = 0;
@@ -749,11 +801,14 @@ static int decrypt_host(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* h, uint3
         }
       }
       worst = std::max(worst, fx_log2(N, nw));
-      mcoef[k] = (uint32_t)((mi + (uint64_t)(k0 % t)) % t);
+      mcoef[k] = (uint32_t)((mi % t + (uint64_t)(k0 % t)) % t);
     }
     if (err) return 1;
     // decode: slot j = evaluation at psi_t^(e_j)
-    host_ntt(c, (int)L + 1, mcoef, false);
+    if (inner_parallel)
+      host_ntt_fwd_threads(c, (int)L + 1, mcoef);
+    else
+      host_ntt(c, (int)L + 1, mcoef, false);
     for (uint32_t j = 0; j < n; ++j) {
       const uint32_t v = mcoef[c->slot_pos[j]];
       slots[(size_t)ci * n + j] = v > (t - 1) / 2 ? (int64_t)v - t : (int64_t)v;

@@ -122,6 +122,7 @@ struct lrhe_sk {
   uint32_t n = 0, L = 0;
   std::vector<int8_t> s;        // ternary coefficients
   std::vector<uint32_t> S;      // [L][n] evaluation form, canonical
+  std::vector<uint32_t> Sm;     // the same in Montgomery form (S R mod q_j), for decryption
 };
 
 struct lrhe_pk {
