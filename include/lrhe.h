@@ -229,8 +229,9 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * on one XCD; 1: as 0 with the twiddles of the next butterfly stage loaded
  * ahead; 2: double-buffered exchange, pair per XCD, unreduced 64-bit inner
  * products; 3: double-buffered exchange with the next digit loaded ahead;
- * 4: as 2 with the digits of each (pair, modulus) item split over two
- * workgroups, the special-prime inverse transforms in a kernel of their own
+ * 4: double-buffered exchange and unreduced 64-bit inner products, with the
+ * digits of each (pair, modulus) item split over two workgroups (in launch
+ * order), the special-prime inverse transforms in a kernel of their own
  * and the division by P split by ciphertext part (more workgroups for tiles
  * too small to fill the GPU; small class only, EINVAL for the large class or
  * a bare key).  These five keys exist in two classes, for tiles of fewer than

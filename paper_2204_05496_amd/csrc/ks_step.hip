@@ -32,7 +32,7 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
   LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
   LRHE_MAC_MODE_CASE(2, LN, LE, 225) /* double buffer, pair per XCD, rotated, 64-bit MAC */   \
   LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */                           \
-  LRHE_MAC_MODE_CASE(4, LN, LE, 481) /* as 2, two workgroups per item (digit halves); small tiles */
+  LRHE_MAC_MODE_CASE(4, LN, LE, 385) /* double buffer, 64-bit MAC, two workgroups per item (digit halves) */
 #endif
 
 template <int LN>
