@@ -235,7 +235,7 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * and the division by P split by ciphertext part (more workgroups for tiles
  * too small to fill the GPU; small class only, EINVAL for the large class or
  * a bare key).  These five keys exist in two classes, for tiles of fewer than
- * "small_below" pairs (default 1024; such launches are latency-bound) and for
+ * "small_below" pairs (default 64; such launches are latency-bound) and for
  * larger tiles: "small.<key>" and "large.<key>" address one class, a bare key
  * sets both and reads the large class.  Defaults: large tiles le_intt 5,
  * le_mac 6, le_moddown 6, le_mask 4 (each 5 where the ring dimension does not

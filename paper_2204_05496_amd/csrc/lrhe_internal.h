@@ -87,7 +87,7 @@ struct Tune {
   Knobs large;
   Knobs small{5, 5, 5, 5, 3};
   uint32_t tile = 4096;
-  uint32_t small_below = 1024;
+  uint32_t small_below = 64;
   const Knobs& knobs(uint64_t tile_pairs) const { return tile_pairs < small_below ? small : large; }
   Knobs& knobs(uint64_t tile_pairs) { return tile_pairs < small_below ? small : large; }
 };

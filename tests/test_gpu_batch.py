@@ -135,7 +135,8 @@ def test_batch_and_server_digit_halves(tiny_setup, P, torch):
     two workgroups, in a planned batch and in the server: every output equals
     the request run alone with the default choices."""
     p, ctx, keys, reqs, alone = tiny_setup
-    before = ctx.tuning()["small"]["mac_mode"]
+    before = ctx.tuning()
+    ctx.tune_set("small_below", 1024)   # every tile of 64 pairs in the small class
     ctx.tune_set("small.mac_mode", P.native.MAC_MODE_HALF)
     try:
         ys = [ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n)) for wl, _, _ in reqs]
@@ -156,7 +157,8 @@ def test_batch_and_server_digit_halves(tiny_setup, P, torch):
             assert np.array_equal(coeff(ctx, y), alone[k]), f"server request {k}"
         srv.close()
     finally:
-        ctx.tune_set("small.mac_mode", before)
+        ctx.tune_set("small.mac_mode", before["small"]["mac_mode"])
+        ctx.tune_set("small_below", before["small_below"])
 
 
 def test_server_admission_by_memory(tiny_setup, P, torch):
