@@ -509,9 +509,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   __shared__ uint32_t lds[(DB ? 2 : 1) * G::LDS_WORDS];
   int par = 0;
   const int L = c.L;
-  // consecutive workgroups go to the 8 XCDs in turn.  MODE 64: the L + 1
-  // workgroups of a pair run on one XCD, one after the other, so the pair's
-  // digits are fetched into that XCD's L2 once.
+  // consecutive workgroups go to the 8 XCDs in turn.  MODE 64: the workgroups
+  // of a pair run on one XCD, one after the other, so the pair's digits are
+  // fetched into that XCD's L2 once.
   uint32_t li = blockIdx.x;
   if constexpr ((MODE & 64) != 0) {
     if (gridDim.x % 8 == 0) li = (li % 8) * (gridDim.x / 8) + li / 8;

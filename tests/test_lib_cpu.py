@@ -148,3 +148,31 @@ def test_geometry_index_split(tmp_path):
                            os.path.join(root, "tests", "geom_check.cpp"), "-o", exe])
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout
+
+
+
+def test_fast_workspace_accumulator_slots(P):
+    """Workspace of the fast matmul: tiles of the small class hold two key-switch
+    accumulators per pair (the digit-halves variant) and large tiles one; with
+    tiles of B pairs the buffer holds max(B, 2 min(B, small_below - 1)) slots,
+    so a large job's small last tile fits whenever it has at most B/2 pairs."""
+    p = WL.PARAMS["tiny"]
+    ctx = P.Context.from_params(p, device=-1)
+    lib = P.native.lib()
+    slot = (ctx.L + 1) * 2 * ctx.n * 4          # bytes of one pair's accumulators
+
+    def size(pairs):                             # one row per pair: classes = 1 .. n
+        b = ctypes.c_uint64()
+        P.native.check(lib.lrhe_workspace_bytes(ctx.h, P.native.WS_MATMUL_FAST, pairs, 100, 1, ctypes.byref(b)))
+        return b.value
+
+    ctx.tune_set("small_below", 1)               # no small class: one slot per pair
+    one16 = size(16)
+    ctx.tune_set("small_below", 64)
+    assert size(16) - one16 == 16 * slot         # 16 pairs, small class: two slots each
+    ctx.tune_set("tile", 64)
+    ctx.tune_set("small_below", 1)
+    base = size(100)                             # tiles of 64 pairs, then 36
+    for below, extra in ((33, 0), (40, 78 - 64), (64, 126 - 64)):
+        ctx.tune_set("small_below", below)
+        assert size(100) - base == extra * slot, below
