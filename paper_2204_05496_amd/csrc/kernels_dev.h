@@ -243,9 +243,11 @@ __device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r1) {
 
 
 // ------------------------------------------------------------------ batched transform
-template <int LOGN, bool INV>
-__global__ __launch_bounds__(Gm<LOGN>::T) void k_ntt(DevCtx c, uint32_t* data, uint32_t nmod, uint32_t mod0) {
-  using G = Gm<LOGN>;
+// One limb per workgroup, at LE_ residues per thread (the forward transform
+// measured fastest at 16, the inverse at 32).
+template <int LOGN, int LE_, bool INV>
+__global__ __launch_bounds__((Geom<LOGN, LE_>::T)) void k_ntt(DevCtx c, uint32_t* data, uint32_t nmod, uint32_t mod0) {
+  using G = Geom<LOGN, LE_>;
   const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
   const size_t p = blockIdx.x;
