@@ -17,9 +17,11 @@
 
 namespace lrhe {
 
-constexpr int LOGE = 5;
+// geometry of the one-transform-per-workgroup kernels outside the key switch
+// (encoding, encryption, model lift): 16 residues per thread up to n = 16384
+// (1024 threads), 32 above; the forward transforms measured fastest there
 template <int LOGN>
-using Gm = Geom<LOGN, LOGE>;
+using Gm = Geom<LOGN, (LOGN <= 14 ? 4 : 5)>;
 
 // ------------------------------------------------------------------ helpers
 // Read/write view of a device array through a buffer resource held in SGPRs:
