@@ -239,7 +239,8 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * larger tiles: "small.<key>" and "large.<key>" address one class, a bare key
  * sets both and reads the large class.  Defaults: large tiles le_intt 5,
  * le_mac 6, le_moddown 6, le_mask 4 (each 5 where the ring dimension does not
- * allow it) and mac_mode 1; small tiles 5/5/5/5 and mac_mode 3.
+ * allow it) and mac_mode 1; small tiles le_intt 5, le_mac, le_moddown and
+ * le_mask 4 (5 where not available) and mac_mode 4.
  * "tile" = pairs per tile (default 4096), "small_below" as above; the
  * workspace size depends on both (small tiles hold two accumulators per pair).
  * No choice changes any result bit.  EINVAL for unknown keys or unavailable

@@ -281,6 +281,13 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
   c->tune.large.le_moddown = le_valid(c->logn, 6) ? 6 : 5;
   c->tune.large.le_mask = le_valid(c->logn, 4) ? 4 : 5;
   c->tune.large.mac_mode = 1;
+  // and for small tiles, as measured on a single inference (16 pairs): the
+  // digit-halves variant at 16 residues per thread
+  c->tune.small.le_intt = 5;
+  c->tune.small.le_mac = le_valid(c->logn, 4) ? 4 : 5;
+  c->tune.small.le_moddown = le_valid(c->logn, 4) ? 4 : 5;
+  c->tune.small.le_mask = le_valid(c->logn, 4) ? 4 : 5;
+  c->tune.small.mac_mode = LRHE_MAC_MODE_HALF;
   // moduli and twiddle tables (data primes, P, t)
   std::vector<uint32_t> all = qs;
   all.push_back(p->t);
