@@ -647,7 +647,10 @@ void ora_pair(const ora_ctx* c, const u64* gk, const u64* gk_ev, const u64* xct,
 }
 
 /* Full Algorithm 1 over rows x classes pairs: result r = i*classes + j is written
- * to output ciphertext r / n (compression = modular sum of the masked ciphertexts). */
+ * to output ciphertext r / n (compression = modular sum of the masked ciphertexts).
+ * Each thread keeps one masked ciphertext at a time and adds it into its output
+ * under a lock, so memory stays bounded at any number of pairs; a sum mod q does
+ * not depend on the order of its terms. */
 void ora_fast_matmul(const ora_ctx* c, const u64* gk, const u64* gk_ev, const u64* xct, const u64* wpt,
                      const u64* bias_t, int rows, int classes, int K, u64* out) {
   const int n = c->n, L = c->L;
@@ -655,15 +658,19 @@ void ora_fast_matmul(const ora_ctx* c, const u64* gk, const u64* gk_ev, const u6
   const long npairs = (long)rows * classes;
   const long nout = (npairs + n - 1) / n;
   memset(out, 0, sizeof(u64) * C * nout);
-  u64* masked = (u64*)malloc(sizeof(u64) * C * npairs);
-#pragma omp parallel for schedule(dynamic)
-  for (long r = 0; r < npairs; ++r) {
-    const int i = (int)(r / classes), j = (int)(r % classes);
-    ora_pair(c, gk, gk_ev, xct + (size_t)i * K * C, wpt + (size_t)j * K * n, K, bias_t[j], (int)(r % n), 0,
-             masked + r * C);
+#pragma omp parallel
+  {
+    u64* masked = (u64*)malloc(sizeof(u64) * C);
+#pragma omp for schedule(dynamic)
+    for (long r = 0; r < npairs; ++r) {
+      const int i = (int)(r / classes), j = (int)(r % classes);
+      ora_pair(c, gk, gk_ev, xct + (size_t)i * K * C, wpt + (size_t)j * K * n, K, bias_t[j], (int)(r % n), 0,
+               masked);
+#pragma omp critical(ora_compress)
+      ora_add(c, out + (r / n) * C, masked, out + (r / n) * C);
+    }
+    free(masked);
   }
-  for (long r = 0; r < npairs; ++r) ora_add(c, out + (r / n) * C, masked + r * C, out + (r / n) * C);
-  free(masked);
 }
 
 /* Standard encrypted matmul (baseline): fct = f feature ciphertexts (individuals in

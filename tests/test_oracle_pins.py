@@ -472,3 +472,53 @@ def test_parameter_sets_are_largest_ntt_primes():
         L = len(p.q)
         assert list(p.q) + [p.P] == ntt_primes(p.n, L + 1)
         assert is_prime(p.t) and p.t % (2 * p.n) == 1
+
+
+def _lift(v, t, centred):
+    v = int(v) % t
+    return v - t if centred and v > (t - 1) // 2 else v
+
+
+def test_mul_plain_centred_lift_bruteforce(o16):
+    """ct x pt lifts each plaintext coefficient (a residue mod t) to its centred
+    representative in (-t/2, t/2] before the negacyclic product mod q_j; the
+    product is recomputed with Python integers by schoolbook.  The residues are
+    chosen so that the [0, t) lift gives a different ciphertext."""
+    n, q, t = 16, N16["q"], N16["t"]
+    g = rng(31)
+    ct = np.stack([np.stack([g.integers(0, qj, n) for qj in q]) for _ in range(2)]).astype(np.uint64)
+    w_t = O.u64(g.integers(0, t, n))
+    w_t[:4] = [t - 1, (t + 1) // 2, (t - 1) // 2, 0]   # both sides of t/2
+    out = np.zeros_like(ct)
+    O.lib().ora_mul_plain(o16.ctx, O.P(np.ascontiguousarray(ct)), O.P(w_t), O.P(out))
+    for centred in (True, False):
+        w = [_lift(v, t, centred) for v in w_t]
+        ref = np.array([[bf.negacyclic(ct[x, j], w, q[j]) for j in range(3)] for x in range(2)], dtype=np.uint64)
+        assert np.array_equal(out, ref) == centred
+
+
+def test_standard_scalar_centred_lift_bruteforce(o16):
+    """Standard baseline: Y_j = sum_k fct_k w_kj + Delta(b_j) with each scalar weight
+    lifted to its centred representative; recomputed with Python integers.  A
+    [0, t) lift of the negative weights gives a different ciphertext."""
+    n, q, t = 16, N16["q"], N16["t"]
+    Q = q[0] * q[1] * q[2]
+    g = rng(32)
+    f, classes = 5, 3
+    fct = np.stack([np.stack([np.stack([g.integers(0, qj, n) for qj in q]) for _ in range(2)])
+                    for _ in range(f)]).astype(np.uint64)
+    W = g.integers(-127, 128, (f, classes))
+    W[0, 0], W[1, 0] = -1, -127
+    b = g.integers(-127, 128, classes)
+    out = o16.standard_matmul(fct, W, b)
+    for centred in (True, False):
+        ok = True
+        for j in range(classes):
+            for x in range(2):
+                for li, qj in enumerate(q):
+                    acc = [sum(int(fct[k, x, li, e]) * _lift(W[k, j], t, centred) for k in range(f)) for e in range(n)]
+                    if x == 0:
+                        bt = int(b[j]) % t
+                        acc[0] += (Q * bt + t // 2) // t      # Delta(b_j) = round(Q b / t) on coefficient 0
+                    ok &= [v % qj for v in acc] == [int(v) for v in out[j, x, li]]
+        assert ok == centred
