@@ -61,8 +61,11 @@ enum {
   LRHE_ENOMEM = -3,   /* device allocation failed or workspace too small */
   LRHE_EAGAIN = -4,   /* server admission refused: over the memory budget */
   LRHE_EDEVICE = -5,  /* HIP runtime error */
-  LRHE_ENOISE = -6    /* decryption noise budget exhausted (debug decrypt) */
+  LRHE_ENOISE = -6    /* decryption differs from the expected plaintext (lrhe_decrypt_check only) */
 };
+
+/* flags of the decryption calls */
+enum { LRHE_CT_HOST = 1 /* the ciphertexts are in host memory (else device memory, copied on `stream`) */ };
 
 typedef struct lrhe_ctx lrhe_ctx;
 typedef struct lrhe_sk lrhe_sk;       /* secret key: host memory only */
@@ -76,15 +79,20 @@ typedef struct {
   uint32_t L;               /* number of data primes, 1..15 */
   const uint32_t* q;        /* L data primes (host array, copied) */
   uint32_t P;               /* special key-switching prime */
-  uint32_t t;               /* plaintext modulus, prime, < 2^30, = 1 mod 2n */
+  uint32_t t;               /* plaintext modulus, prime, = 1 mod 2n, < 2^31 and < 2 q_i for every q_i and P */
   uint32_t allow_insecure;  /* nonzero: accept log2(Q P) above the 128-bit bound */
 } lrhe_params;
 
 /* Thread-local message describing the last error. */
 const char* lrhe_last_error(void);
 
-/* Create a context on HIP device `device`: validates the parameters
- * (EPARAM), derives roots, twiddle and RNS tables and uploads them.
+/* Create a context on HIP device `device` (the public values {n, T} of the
+ * protocol, section "Private inference protocol"; the ring and moduli follow
+ * the BFV scheme the paper runs, section "Privacy-preserving model
+ * evaluation"): validates the parameters (EPARAM), derives roots, twiddle and
+ * RNS tables and uploads them.  t must also stay below 2^31 and below twice
+ * every ciphertext prime (plaintext values are lifted into each q_i by their
+ * centred representative).
  * device < 0 creates a host-only (client) context: key generation, key
  * export, host decryption and host transforms work; device calls return
  * LRHE_EDEVICE. */
@@ -104,14 +112,20 @@ void lrhe_sk_destroy(lrhe_sk* sk);
 void lrhe_pk_destroy(lrhe_pk* pk);
 void lrhe_gk_destroy(lrhe_gk* gk);
 
-/* Workspace sizes (bytes) of the device calls below. */
+/* Workspace sizes (bytes) of the device calls below (caller-allocated device
+ * memory; a call given less returns LRHE_ENOMEM). */
 enum { LRHE_WS_ENCRYPT_ROWS = 1, LRHE_WS_ENCRYPT_COLS = 2, LRHE_WS_MATMUL_FAST = 3, LRHE_WS_MATMUL_STANDARD = 4 };
 int lrhe_workspace_bytes(const lrhe_ctx* ctx, int op, uint32_t rows, uint32_t f, uint32_t classes, uint64_t* bytes);
 
-/* Encode and encrypt X (device int64, rows x f, row-major; values taken mod t)
- * in the fast layout of the protocol: row i, chunk k holds X[i][k n .. k n + n)
- * in its slots (zero past f) and is ciphertext i K + k of ct_out, K = ceil(f/n).
- * Randomness: stream seed `seed`, ciphertext id id0 + i K + k. */
+/* Client: encode and encrypt the scaled feature matrix (section "Private
+ * inference protocol": n features per polynomial, |X| x ceil(f/n) plaintexts,
+ * each encrypted with the client's public key).  X: device int64, rows x f,
+ * row-major, values taken mod t.  Fast layout: row i, chunk k holds
+ * X[i][k n .. k n + n) in its slots (zero past f) and is ciphertext i K + k of
+ * ct_out (device, rows K ciphertexts, caller-owned), K = ceil(f/n).
+ * Randomness: stream seed `seed`, ciphertext id id0 + i K + k.
+ * Errors: EINVAL (null, rows or f = 0), ENOMEM (workspace too small),
+ * EDEVICE (host-only context or HIP error). */
 int lrhe_encrypt_rows(lrhe_ctx* ctx, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f,
                       uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes, void* stream);
 /* Standard layout: ciphertext k (k < f) holds column X[.][k] in slots 0..rows-1
@@ -119,15 +133,19 @@ int lrhe_encrypt_rows(lrhe_ctx* ctx, const lrhe_pk* pk, const int64_t* X, uint32
 int lrhe_encrypt_cols(lrhe_ctx* ctx, const lrhe_pk* pk, const int64_t* X, uint32_t rows, uint32_t f,
                       uint64_t seed, uint64_t id0, uint32_t* ct_out, void* ws, size_t ws_bytes, void* stream);
 
-/* Server-side model encoding: W (device int64, f x classes, row-major, the
- * paper's f x |Y| weight matrix) transposed and packed n weights per
- * plaintext, plus the all-slot bias plaintexts (bias: host int64[classes]).
- * Also keeps the scalar weights the standard baseline needs. */
+/* Server: encode the model (section "Private inference protocol": the server
+ * transposes W, packs it into |Y| x ceil(f/n) plaintexts, and turns each bias
+ * into an all-slot plaintext).  W: device int64, f x classes, row-major (the
+ * paper's f x |Y| weight matrix), values taken mod t; bias: host
+ * int64[classes] or NULL (zero).  Also keeps the scalar weights the standard
+ * baseline needs.  The model lives in library-owned device memory until
+ * lrhe_model_destroy.  Errors: EINVAL, EDEVICE (allocation or HIP error). */
 int lrhe_model_create(lrhe_ctx* ctx, const int64_t* W, const int64_t* bias, uint32_t f, uint32_t classes,
                       void* stream, lrhe_model** out);
 void lrhe_model_destroy(lrhe_model* m);
 
-/* Algorithm 1: Y^ = X^ x W- + B-.  xct: rows x K ciphertexts from
+/* Server: Algorithm 1 (section "Matrix multiplication algorithm"),
+ * Y^ = X^ x W- + B-.  xct: rows x K ciphertexts from
  * lrhe_encrypt_rows with the model's f.  y_out: ceil(rows classes / n)
  * ciphertexts; result (i, j) in ciphertext (i classes + j) / n, slot
  * (i classes + j) mod n.  ws: lrhe_workspace_bytes(LRHE_WS_MATMUL_FAST). */
@@ -169,42 +187,86 @@ int lrhe_batch_run(lrhe_ctx* ctx, const lrhe_gk* gk, lrhe_batch* b, void* ws, si
 int lrhe_batch_capture(lrhe_ctx* ctx, const lrhe_gk* gk, lrhe_batch* b, void* ws, size_t ws_bytes, void* stream);
 void lrhe_batch_destroy(lrhe_batch* b);
 
-/* Continuous-batching server: the Galois keys stay resident; a worker thread
+/* Continuous-batching server (section "Privacy-preserving model evaluation":
+ * many individuals' predictions at once; Algorithm 1's pairs are independent,
+ * section "Matrix multiplication algorithm"): the Galois keys stay resident; a worker thread
  * packs the next `tile` pending pairs of the admitted requests (arrival order)
  * into each tile, so requests that arrive while others run join the next tile.
  * hbm_budget bounds the server's partial-sum arena; a request is admitted only
  * if its partial sums fit (else LRHE_EAGAIN: resubmit later).  Inputs and
  * outputs are caller-owned device buffers that must stay valid until done. */
 int lrhe_server_create(lrhe_ctx* ctx, const lrhe_gk* gk, size_t hbm_budget, lrhe_server** out);
+/* `stream`: the stream on which the caller wrote xct (NULL = the default
+ * stream); the server's first tile with this request waits for the work queued
+ * there at the time of the call, so the caller need not synchronise first. */
 int lrhe_server_submit(lrhe_server* s, const lrhe_model* model, const uint32_t* xct, uint32_t rows, uint32_t* y,
-                       uint64_t* req_id);
+                       void* stream, uint64_t* req_id);
 /* The same for a request under another client's keys (gk of the same context,
  * resident until the request is done); requests of different clients share tiles. */
 int lrhe_server_submit_keys(lrhe_server* s, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct,
-                            uint32_t rows, uint32_t* y, uint64_t* req_id);
-/* done = 1 once the request's outputs are written; latency_s = submit -> completion. */
+                            uint32_t rows, uint32_t* y, void* stream, uint64_t* req_id);
+/* done = 1 once the request's outputs are written (and visible to any stream);
+ * latency_s = submit -> completion. */
 int lrhe_server_poll(lrhe_server* s, uint64_t req_id, int* done, double* latency_s);
+/* Forget a finished request (EINVAL while it is not done): the server keeps a
+ * record of every request until it is released or the server is destroyed. */
+int lrhe_server_release(lrhe_server* s, uint64_t req_id);
 /* Block until every admitted request is done. */
 int lrhe_server_drain(lrhe_server* s);
-int lrhe_server_stats(lrhe_server* s, uint64_t* ticks, uint64_t* pairs, uint32_t* free_slots, uint32_t* tile);
+/* ticks run, pairs computed, free partial-sum slots, pairs per tile, request records held. */
+int lrhe_server_stats(lrhe_server* s, uint64_t* ticks, uint64_t* pairs, uint32_t* free_slots, uint32_t* tile,
+                      uint32_t* held);
 void lrhe_server_destroy(lrhe_server* s);
 
-/* Standard baseline: fct = f ciphertexts from lrhe_encrypt_cols;
- * y_out[j] = sum_k fct[k] w_kj + B_j (classes ciphertexts); score (i, j) is
- * slot i of y_out[j]. */
+/* Server: the standard encrypted matrix multiplication the paper compares
+ * against (section "Comparison to standard LR"; the paper does not spell it
+ * out: individuals in the slots, one ciphertext per feature, scalar weights,
+ * no rotations).  fct: f device ciphertexts from lrhe_encrypt_cols; y_out:
+ * device, classes ciphertexts, y_out[j] = sum_k fct[k] w_kj + B_j; score
+ * (i, j) is slot i of y_out[j].  ws is unused (may be NULL).
+ * Errors: EINVAL (null), EDEVICE. */
 int lrhe_matmul_standard(lrhe_ctx* ctx, const lrhe_model* model, const uint32_t* fct, uint32_t* y_out,
                          void* ws, size_t ws_bytes, void* stream);
 
-/* Client decryption: copies `count` ciphertexts from the device, decrypts them
- * on the host with the secret key and decodes the slots, centred into
- * (-t/2, t/2] (slots: host int64[count][n]).  budgets (optional, host
- * double[count]): remaining noise budget log2(Q/2) - log2 max|[t x]_Q| in bits. */
+/* Client decryption (section "Private inference protocol": the client decrypts
+ * and decodes the result ciphertexts): copies `count` ciphertexts from the
+ * device, decrypts them on the host with the secret key and decodes the slots,
+ * centred into (-t/2, t/2] (slots: host int64[count][n]).  budgets
+ * (optional, host double[count]): remaining noise budget
+ * log2(Q/2) - log2 max|[t x]_Q| in bits.  The secret key never leaves the host. */
 int lrhe_decrypt_slots(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, int64_t* slots,
                        double* budgets, void* stream);
 
-/* Same as lrhe_decrypt_slots for ciphertexts already in host memory (same layout). */
+/* Same as lrhe_decrypt_slots for ciphertexts already in host memory (same layout;
+ * for example ciphertexts read back from the wire format). */
 int lrhe_decrypt_slots_host(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, int64_t* slots,
                             double* budgets);
+/* Client: decrypt the class scores of Algorithm 1 (section "Private inference
+ * protocol"; result r = i classes + j sits in output ciphertext r / n, slot
+ * r mod n, as Algorithm 1 fills its outputs).  y: the ceil(rows classes / n)
+ * output ciphertexts of lrhe_matmul_fast (device memory, or host memory with
+ * LRHE_CT_HOST in flags).  scores: host int64[rows][classes], centred into
+ * (-t/2, t/2]; the predicted class of row i is the argmax of its row (section
+ * "Approximation of non-linear function in private inference").
+ * min_budget_bits (optional): the smallest remaining noise budget over the
+ * ciphertexts, in bits.  Errors: EINVAL (null, empty, unknown flags), EDEVICE. */
+int lrhe_decrypt_scores(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* y, uint32_t rows, uint32_t classes,
+                        uint32_t flags, int64_t* scores, double* min_budget_bits, void* stream);
+/* The same for the standard baseline's outputs (section "Comparison to
+ * standard LR"): y holds `classes` ciphertexts, score (i, j) is slot i of
+ * ciphertext j (rows <= n). */
+int lrhe_decrypt_scores_standard(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* y, uint32_t rows,
+                                 uint32_t classes, uint32_t flags, int64_t* scores, double* min_budget_bits,
+                                 void* stream);
+/* Debug decryption given the expected plaintext: decrypts `count` ciphertexts
+ * (flags as above) and compares every slot with expected (host
+ * int64[count][n], compared mod t).  Returns LRHE_ENOISE when any slot
+ * differs, which in BFV means the noise grew past the budget; mismatches
+ * (optional) receives the number of differing slots, budgets (optional, host
+ * double[count]) the remaining budgets. */
+int lrhe_decrypt_check(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, const int64_t* expected,
+                       uint32_t flags, double* budgets, uint64_t* mismatches, void* stream);
+
 /* Host (client-side) transform of one polynomial in place, modulus index
  * mod_index (0..L-1 data primes, L = P, L+1 = t): forward maps canonical
  * coefficients to evaluations at psi^(2 brv(k)+1) stored at index k (the
@@ -262,6 +324,13 @@ int lrhe_autotune_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model
 void lrhe_prof_enable(int on);
 void lrhe_prof_reset(void);
 int lrhe_prof_get(const char* kernel, uint64_t* launches, double* total_ms);
+
+/* Allocation fault injection (failure handling tests): the k-th device
+ * allocation of the library from now on fails as if out of memory, so the call
+ * that makes it returns LRHE_EDEVICE (LRHE_ENOMEM for the server) and leaves no
+ * partial object; k = 0 disarms.  The environment variable LRHE_FAULT_ALLOC
+ * gives the initial k.  Returns the previous k; k < 0 only reads it. */
+int64_t lrhe_fault_inject(int64_t k);
 
 /* Keys in canonical coefficient form on the host: pk as uint32 [2][L][n];
  * gk as uint32 [ngal][L digits][2][L+1 moduli][n] (last modulus = P). */

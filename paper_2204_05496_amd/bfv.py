@@ -194,15 +194,35 @@ class Context:
         N.check(N.lib().lrhe_decrypt_slots_host(self.h, keys.sk, N.ptr(ct_host), cnt, N.ptr(slots), N.ptr(bud)))
         return slots, bud
 
+    def _scores(self, fn, keys: Keys, y, rows: int, classes: int):
+        S = np.zeros((rows, classes), dtype=np.int64)
+        bud = ctypes.c_double()
+        if isinstance(y, np.ndarray):
+            y = np.ascontiguousarray(y, dtype=np.uint32)
+            N.check(fn(self.h, keys.sk, N.ptr(y), rows, classes, N.CT_HOST, N.ptr(S), ctypes.byref(bud), None))
+        else:
+            N.check(fn(self.h, keys.sk, N.ptr(y.contiguous()), rows, classes, 0, N.ptr(S), ctypes.byref(bud),
+                       _stream()))
+        return S, bud.value
+
     def scores_fast(self, keys: Keys, y, rows: int, classes: int):
-        slots, bud = self.decrypt_slots(keys, y)
-        r = np.arange(rows * classes)
-        S = slots[r // self.n, r % self.n].reshape(rows, classes)
-        return S, float(bud.min())
+        """Class scores of Algorithm 1's outputs (device tensor or host uint32 array)."""
+        return self._scores(N.lib().lrhe_decrypt_scores, keys, y, rows, classes)
 
     def scores_standard(self, keys: Keys, y, rows: int):
-        slots, bud = self.decrypt_slots(keys, y)
-        return slots[:, :rows].T.copy(), float(bud.min())
+        """Class scores of the standard baseline's outputs (one ciphertext per class)."""
+        return self._scores(N.lib().lrhe_decrypt_scores_standard, keys, y, rows, y.shape[0])
+
+    def decrypt_check(self, keys: Keys, ct, expected):
+        """Debug decryption against the expected slot values: raises LrheError with
+        code LRHE_ENOISE when any slot differs.  Returns the noise budgets."""
+        exp = np.ascontiguousarray(expected, dtype=np.int64)
+        cnt = ct.shape[0]
+        bud = np.zeros(cnt, dtype=np.float64)
+        bad = ctypes.c_uint64()
+        N.check(N.lib().lrhe_decrypt_check(self.h, keys.sk, N.ptr(ct.contiguous()), cnt, N.ptr(exp), 0, N.ptr(bud),
+                                           ctypes.byref(bad), _stream()))
+        return bud
 
     def host_transform(self, a: np.ndarray, mod_index: int, inverse: bool = False) -> np.ndarray:
         a = np.ascontiguousarray(a, dtype=np.uint32).copy()
@@ -321,24 +341,30 @@ class Server:
         h = ctypes.c_void_p()
         N.check(N.lib().lrhe_server_create(ctx.h, keys.gk, hbm_budget, ctypes.byref(h)))
         self.h = h
-        self._keep = {}
-        self._held = [keys]   # key sets stay alive while the server may use them
+        self._keep = {}       # request id -> buffers, model and keys it uses, until released
+        self._keys = keys     # the server's own key set stays alive with it
 
     def submit(self, model: Model, xct, rows: int, y, keys: Keys = None):
         """Returns the request id, or None when admission is refused (LRHE_EAGAIN).
-        `keys`: the client's keys when they are not the server's."""
+        `keys`: the client's keys when they are not the server's.  The server waits
+        for the work queued on the current torch stream (the encryption of xct)."""
         rid = ctypes.c_uint64()
         if keys is not None:
-            self._held.append(keys)
             code = N.lib().lrhe_server_submit_keys(self.h, keys.gk, model.handle, N.ptr(xct), rows, N.ptr(y),
-                                                   ctypes.byref(rid))
+                                                   _stream(), ctypes.byref(rid))
         else:
-            code = N.lib().lrhe_server_submit(self.h, model.handle, N.ptr(xct), rows, N.ptr(y), ctypes.byref(rid))
+            code = N.lib().lrhe_server_submit(self.h, model.handle, N.ptr(xct), rows, N.ptr(y), _stream(),
+                                              ctypes.byref(rid))
         if code == N.LRHE_EAGAIN:
             return None
         N.check(code)
-        self._keep[rid.value] = (xct, y, model)
+        self._keep[rid.value] = (xct, y, model, keys)
         return rid.value
+
+    def release(self, rid: int):
+        """Forget a finished request: the server's record and the buffers held for it."""
+        N.check(N.lib().lrhe_server_release(self.h, rid))
+        self._keep.pop(rid, None)
 
     def poll(self, rid: int):
         done, lat = ctypes.c_int(), ctypes.c_double()
@@ -349,9 +375,10 @@ class Server:
         N.check(N.lib().lrhe_server_drain(self.h))
 
     def stats(self) -> dict:
-        t, p, f, b = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
-        N.check(N.lib().lrhe_server_stats(self.h, ctypes.byref(t), ctypes.byref(p), ctypes.byref(f), ctypes.byref(b)))
-        return {"ticks": t.value, "pairs": p.value, "free_slots": f.value, "tile": b.value}
+        t, p, f, b, hd = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        N.check(N.lib().lrhe_server_stats(self.h, ctypes.byref(t), ctypes.byref(p), ctypes.byref(f), ctypes.byref(b),
+                                          ctypes.byref(hd)))
+        return {"ticks": t.value, "pairs": p.value, "free_slots": f.value, "tile": b.value, "held": hd.value}
 
     def close(self):
         if getattr(self, "h", None):

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +44,45 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 extern "C" const char* lrhe_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ allocation fault injection
+// Countdown to a failing device allocation: k > 0 means the k-th allocation
+// from now fails (then the countdown is spent); 0 means disarmed.  The initial
+// value comes from the environment variable LRHE_FAULT_ALLOC (read once).
+static std::atomic<int64_t> g_fault{0};
+static std::once_flag g_fault_env;
+static void fault_env_init() {
+  std::call_once(g_fault_env, [] {
+    if (const char* v = std::getenv("LRHE_FAULT_ALLOC")) {
+      const long long k = std::atoll(v);
+      if (k > 0) g_fault.store(k);
+    }
+  });
+}
+static bool fault_fires() {
+  fault_env_init();
+  int64_t k = g_fault.load();
+  while (k > 0) {
+    if (g_fault.compare_exchange_weak(k, k - 1)) return k == 1;
+  }
+  return false;
+}
+namespace lrhe {
+hipError_t dev_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_fires()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  if (fault_fires()) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes, s);
+}
+}  // namespace lrhe
+extern "C" int64_t lrhe_fault_inject(int64_t k) {
+  fault_env_init();
+  return k >= 0 ? g_fault.exchange(k) : g_fault.load();
+}
 
 // ------------------------------------------------------------------ number theory (host)
 static uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
@@ -118,7 +160,7 @@ static double security_bound_bits(uint32_t n) {
 // ------------------------------------------------------------------ host transforms
 // The host runs the very same pass functions as the kernels, one emulated
 // thread at a time, with the exchange done through a plain array.
-template <int LOGN>
+template <int LOGN, bool STRICT = false>
 static void host_ntt_t(uint32_t* a, const uint32_t* tw, const Mod& m, bool inverse) {
   using G = Geom<LOGN, 5>;
   std::vector<uint32_t> X((size_t)G::N), tmp((size_t)G::N);
@@ -131,17 +173,19 @@ static void host_ntt_t(uint32_t* a, const uint32_t* tw, const Mod& m, bool inver
       for (int e = 0; e < G::E; ++e) tmp[G::idx(p, t, e)] = X[(size_t)t * G::E + e];
   };
   std::copy(a, a + G::N, tmp.begin());
+  if (STRICT)   // canonical input
+    for (int i = 0; i < G::N; ++i) tmp[i] %= m.q;
   if (!inverse) {
     for (int p = 0; p < G::NPASS; ++p) {
       load(p);
-      for (int t = 0; t < G::T; ++t) fwd_pass<G>(p, t, &X[(size_t)t * G::E], tw, m.q, m.qinv);
+      for (int t = 0; t < G::T; ++t) fwd_pass<G, false, STRICT>(p, t, &X[(size_t)t * G::E], tw, m.q, m.qinv);
       store(p);
     }
-    for (int i = 0; i < G::N; ++i) a[i] = red2(tmp[i], m.q);
+    for (int i = 0; i < G::N; ++i) a[i] = STRICT ? tmp[i] : red2(tmp[i], m.q);
   } else {
     for (int p = G::NPASS - 1; p >= 0; --p) {
       load(p);
-      for (int t = 0; t < G::T; ++t) inv_pass<G>(p, t, &X[(size_t)t * G::E], tw, m.q, m.qinv);
+      for (int t = 0; t < G::T; ++t) inv_pass<G, false, STRICT>(p, t, &X[(size_t)t * G::E], tw, m.q, m.qinv);
       store(p);
     }
     for (int i = 0; i < G::N; ++i) a[i] = red1(mulm(tmp[i], m.ninv_m, m.q, m.qinv), m.q);
@@ -218,14 +262,15 @@ static void host_ntt_fwd_threads(const lrhe_ctx* c, int mi, uint32_t* a) {
 static void host_ntt_passes(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) {
   const uint32_t* tb = (inverse ? c->h_itw.data() : c->h_tw.data()) + (size_t)mi * c->n;
   const Mod& m = c->mods[mi];
+  // moduli of 2^30 and above (only t can be one) run the canonical-residue passes
+  const bool strict = m.q >= (1u << 30);
+#define LRHE_HOST_NTT_CASE(LN) \
+  case LN: strict ? host_ntt_t<LN, true>(a, tb, m, inverse) : host_ntt_t<LN>(a, tb, m, inverse); break;
   switch (c->logn) {
-    case 10: host_ntt_t<10>(a, tb, m, inverse); break;
-    case 11: host_ntt_t<11>(a, tb, m, inverse); break;
-    case 12: host_ntt_t<12>(a, tb, m, inverse); break;
-    case 13: host_ntt_t<13>(a, tb, m, inverse); break;
-    case 14: host_ntt_t<14>(a, tb, m, inverse); break;
-    case 15: host_ntt_t<15>(a, tb, m, inverse); break;
+    LRHE_HOST_NTT_CASE(10) LRHE_HOST_NTT_CASE(11) LRHE_HOST_NTT_CASE(12)
+    LRHE_HOST_NTT_CASE(13) LRHE_HOST_NTT_CASE(14) LRHE_HOST_NTT_CASE(15)
   }
+#undef LRHE_HOST_NTT_CASE
 }
 
 // ------------------------------------------------------------------ context
@@ -252,10 +297,13 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
       if (qs[k] == q) return fail(LRHE_EPARAM, "modulus %u repeated", q);
     logqp += std::log2((double)q);
   }
-  if (p->t < 3 || p->t >= (1u << 30) || !is_prime(p->t) || (p->t - 1) % (2 * n))
-    return fail(LRHE_EPARAM, "t = %u: must be a prime < 2^30 that is 1 mod 2n", p->t);
-  for (uint32_t q : qs)
+  if (p->t < 3 || p->t >= (1u << 31) || !is_prime(p->t) || (p->t - 1) % (2 * n))
+    return fail(LRHE_EPARAM, "t = %u: must be a prime < 2^31 that is 1 mod 2n", p->t);
+  for (uint32_t q : qs) {
     if (q == p->t) return fail(LRHE_EPARAM, "t equals a ciphertext modulus");
+    // the centred lift of a residue mod t into q, (t-1)/2 or v - t + q, must be a residue mod q
+    if ((uint64_t)p->t >= 2ull * q) return fail(LRHE_EPARAM, "t = %u is not below 2 q for modulus %u", p->t, q);
+  }
   if (!p->allow_insecure && logqp > security_bound_bits(n))
     return fail(LRHE_EPARAM, "log2(Q P) = %.1f exceeds the 128-bit bound %.0f for n = %u (set allow_insecure)",
                 logqp, security_bound_bits(n), n);
@@ -385,7 +433,7 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
   hipError_t err = hipSetDevice(device);
   if (err != hipSuccess) { delete c; return fail(LRHE_EDEVICE, "hipSetDevice(%d): %s", device, hipGetErrorString(err)); }
   auto up = [&](uint32_t** dst, const std::vector<uint32_t>& src) -> hipError_t {
-    hipError_t e2 = hipMalloc((void**)dst, src.size() * 4);
+    hipError_t e2 = dev_malloc((void**)dst, src.size() * 4);
     if (e2 != hipSuccess) return e2;
     return hipMemcpy(*dst, src.data(), src.size() * 4, hipMemcpyHostToDevice);
   };
@@ -519,7 +567,7 @@ extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk*
   }
   const bool dev = c->device >= 0;
   hipError_t err = dev ? hipSetDevice(c->device) : hipSuccess;
-  if (err == hipSuccess && dev) err = hipMalloc((void**)&pk->d, pk->h.size() * 4);
+  if (err == hipSuccess && dev) err = dev_malloc((void**)&pk->d, pk->h.size() * 4);
   if (err != hipSuccess) {
     delete sk;
     delete pk;
@@ -572,7 +620,7 @@ extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk*
       mont[x] = to_mont(gk->h[x], c->mods[r]);
     }
     if (dev) {
-      err = hipMalloc((void**)&gk->d, gk->words * 4);
+      err = dev_malloc((void**)&gk->d, gk->words * 4);
       if (err == hipSuccess) err = hipMemcpy(gk->d, mont.data(), gk->words * 4, hipMemcpyHostToDevice);
     }
   }
@@ -856,6 +904,82 @@ extern "C" int lrhe_decrypt_slots_host(lrhe_ctx* c, const lrhe_sk* sk, const uin
   return decrypt_host(c, sk, ct, count, slots, budgets);
 }
 
+// ciphertexts at ct: device memory copied over on `stream`, or host memory
+// (flags & LRHE_CT_HOST); decrypted and decoded into slots [count][n]
+static int decrypt_any(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* ct, uint32_t count, uint32_t flags,
+                       void* stream, std::vector<int64_t>& slots, std::vector<double>& bud) {
+  if (flags & ~(uint32_t)LRHE_CT_HOST) return fail(LRHE_EINVAL, "unknown flags 0x%x", flags);
+  slots.assign((size_t)count * c->n, 0);
+  bud.assign(count, 0.0);
+  if (flags & LRHE_CT_HOST) return decrypt_host(c, sk, ct, count, slots.data(), bud.data());
+  NEED_DEVICE(c);
+  std::vector<uint32_t> h((size_t)count * 2 * c->L * c->n);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(h.data(), ct, h.size() * 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return decrypt_host(c, sk, h.data(), count, slots.data(), bud.data());
+}
+
+extern "C" int lrhe_decrypt_scores(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* y, uint32_t rows, uint32_t classes,
+                                   uint32_t flags, int64_t* scores, double* min_budget_bits, void* stream) {
+  if (!c || !sk || !y || !scores) return fail(LRHE_EINVAL, "null argument");
+  if (rows == 0 || classes == 0) return fail(LRHE_EINVAL, "empty score matrix");
+  const uint64_t npairs = (uint64_t)rows * classes;
+  const uint64_t nout = (npairs + c->n - 1) / c->n;
+  if (nout > 0xffffffffull) return fail(LRHE_EINVAL, "too many results");
+  std::vector<int64_t> slots;
+  std::vector<double> bud;
+  const int rc = decrypt_any(c, sk, y, (uint32_t)nout, flags, stream, slots, bud);
+  if (rc != LRHE_OK) return rc;
+  // result r = i classes + j of Algorithm 1: output ciphertext r / n, slot r mod n;
+  // slots [count][n] are contiguous, so that is slots[r]
+  std::copy(slots.begin(), slots.begin() + npairs, scores);
+  if (min_budget_bits) *min_budget_bits = *std::min_element(bud.begin(), bud.end());
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_decrypt_scores_standard(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* y, uint32_t rows,
+                                            uint32_t classes, uint32_t flags, int64_t* scores,
+                                            double* min_budget_bits, void* stream) {
+  if (!c || !sk || !y || !scores) return fail(LRHE_EINVAL, "null argument");
+  if (rows == 0 || classes == 0) return fail(LRHE_EINVAL, "empty score matrix");
+  if (rows > c->n) return fail(LRHE_EINVAL, "standard layout: rows %u > n %u", rows, c->n);
+  std::vector<int64_t> slots;
+  std::vector<double> bud;
+  const int rc = decrypt_any(c, sk, y, classes, flags, stream, slots, bud);
+  if (rc != LRHE_OK) return rc;
+  // score (i, j) is slot i of output ciphertext j
+  for (uint32_t i = 0; i < rows; ++i)
+    for (uint32_t j = 0; j < classes; ++j) scores[(size_t)i * classes + j] = slots[(size_t)j * c->n + i];
+  if (min_budget_bits) *min_budget_bits = *std::min_element(bud.begin(), bud.end());
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_decrypt_check(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t* ct, uint32_t count,
+                                  const int64_t* expected, uint32_t flags, double* budgets, uint64_t* mismatches,
+                                  void* stream) {
+  if (!c || !sk || !ct || !expected) return fail(LRHE_EINVAL, "null argument");
+  if (count == 0) return fail(LRHE_EINVAL, "no ciphertexts");
+  std::vector<int64_t> slots;
+  std::vector<double> bud;
+  const int rc = decrypt_any(c, sk, ct, count, flags, stream, slots, bud);
+  if (rc != LRHE_OK) return rc;
+  if (budgets) std::copy(bud.begin(), bud.end(), budgets);
+  // expected slot values are compared as residues mod t
+  const int64_t t = c->t;
+  uint64_t bad = 0;
+  size_t first = 0;
+  for (size_t k = 0; k < slots.size(); ++k) {
+    const int64_t d = ((slots[k] - expected[k]) % t + t) % t;
+    if (d != 0 && bad++ == 0) first = k;
+  }
+  if (mismatches) *mismatches = bad;
+  if (bad)
+    return fail(LRHE_ENOISE, "decryption differs from the expected plaintext in %llu slots (first: ciphertext %zu, "
+                "slot %zu): the noise exceeded the budget", (unsigned long long)bad, first / c->n, first % c->n);
+  return LRHE_OK;
+}
+
 extern "C" int lrhe_host_transform(lrhe_ctx* c, uint32_t mod_index, uint32_t* a, int inverse) {
   if (!c || !a || mod_index > c->L + 1) return fail(LRHE_EINVAL, "bad argument");
   host_ntt_passes(c, (int)mod_index, a, inverse != 0);
@@ -924,9 +1048,9 @@ extern "C" int lrhe_model_create(lrhe_ctx* c, const int64_t* W, const int64_t* b
       db[(size_t)j * L + i] = (uint32_t)((a + rnd % md.q) % md.q);
     }
   }
-  hipError_t err = hipMalloc((void**)&m->wpt, (size_t)classes * m->K * L * n * 4);
-  if (err == hipSuccess) err = hipMalloc((void**)&m->wsc, (size_t)f * std_class_pad(classes) * L * 4);
-  if (err == hipSuccess) err = hipMalloc((void**)&m->dbias, db.size() * 4);
+  hipError_t err = dev_malloc((void**)&m->wpt, (size_t)classes * m->K * L * n * 4);
+  if (err == hipSuccess) err = dev_malloc((void**)&m->wsc, (size_t)f * std_class_pad(classes) * L * 4);
+  if (err == hipSuccess) err = dev_malloc((void**)&m->dbias, db.size() * 4);
   if (err == hipSuccess) err = hipMemcpy(m->dbias, db.data(), db.size() * 4, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = launch_model_encode(c, W, f, classes, m->wpt, m->wsc, (hipStream_t)stream);
   if (err == hipSuccess) err = hipStreamSynchronize((hipStream_t)stream);

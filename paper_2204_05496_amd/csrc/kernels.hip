@@ -69,7 +69,7 @@ hipError_t launch_model_encode(const lrhe_ctx* c, const int64_t* W, uint32_t f, 
   const uint32_t K = (uint32_t)((f + n - 1) / n);
   const uint64_t npt = (uint64_t)classes * K;
   uint32_t* mt = nullptr;
-  hipError_t err = hipMallocAsync((void**)&mt, npt * n * 4, s);
+  hipError_t err = dev_malloc_async((void**)&mt, npt * n * 4, s);
   if (err != hipSuccess) return err;
   LRHE_DISPATCH(c->logn, {
     k_encode<LN><<<(unsigned)npt, Gm<LN>::T, 0, s>>>(c->dc, W, SRC_WT, 0, f, K, classes, mt, nullptr);

@@ -138,15 +138,16 @@ __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TW& tw
   for (int e = 0; e < G::E; ++e) x[e] = red2(x[e], m.q);
 }
 
-// inverse transform: x in last-pass layout with values < 2q; returns canonical
-// coefficients in pass-0 layout
-template <class G, bool DB = false, bool PF = false, class TW = TwView>
+// inverse transform: x in last-pass layout with values < 2q (canonical with
+// STRICT, for moduli of 2^30 and above); returns canonical coefficients in
+// pass-0 layout
+template <class G, bool DB = false, bool PF = false, class TW = TwView, bool STRICT = false>
 __device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const TW& itw, const Mod& m, int t,
                                         int* par = nullptr) {
 #pragma unroll
   for (int p = G::NPASS - 1; p >= 0; --p) {
     if (p < G::NPASS - 1) xchg<G, DB>(lds, p + 1, p, x, t, par);
-    inv_pass<G, PF>(p, t, x, itw, m.q, m.qinv);
+    inv_pass<G, PF, STRICT>(p, t, x, itw, m.q, m.qinv);
   }
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = red1(mulm(x[e], m.ninv_m, m.q, m.qinv), m.q);
@@ -306,8 +307,12 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encode(DevCtx c, const int64_t*
     }
     x[e] = mod_t_i64(v, tm);
   }
+  // the mod-t transform: lazy reduction where 4t fits in 32 bits, canonical
+  // residues throughout for t of 2^30 and above (the paper's plaintext modulus
+  // t0 = 1073872897)
   const int mt = c.L + 1;
-  ntt_inv<G>(x, lds, twv(c.itw, mt, G::N), c.mod[mt], t);
+  if (tm < (1u << 30)) ntt_inv<G>(x, lds, twv(c.itw, mt, G::N), c.mod[mt], t);
+  else ntt_inv<G, false, false, TwView, true>(x, lds, twv(c.itw, mt, G::N), c.mod[mt], t);
   store0<G>(DBuf(m_out + ci * G::N, G::N), x, t);
   if (rnd) {
     const DBuf r(rnd + ci * G::N, G::N);
@@ -375,7 +380,8 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
     const uint32_t k = idx0<G>(e, t);
-    const uint32_t delta = addm(red1(mulm(mv[k], c.qdivt_m[j], md.q, md.qinv), md.q), rv[k], md.q);
+    // rnd < t < 2 q_j: one conditional subtraction makes it a residue mod q_j
+    const uint32_t delta = addm(red1(mulm(mv[k], c.qdivt_m[j], md.q, md.qinv), md.q), red1(rv[k], md.q), md.q);
     x[e] = addm(small_mod(su[G::N + k], md.q), delta, md.q);
   }
   ntt_fwd<G>(x, lds, tw, md, t);
@@ -396,7 +402,8 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_
 }
 
 // ------------------------------------------------------------------ model encoding
-// centred lift of a residue mod t into q, Montgomery form
+// centred lift of a residue v < t into q, Montgomery form: v itself up to
+// (t-1)/2, v - t + q above (both in [0, q) because t < 2q)
 __device__ __forceinline__ uint32_t lift_mont(uint32_t v, uint32_t t, const Mod& md) {
   const uint32_t l = v > (t - 1) / 2 ? v + md.q - t : v;
   return to_mont(l, md);

@@ -147,6 +147,12 @@ namespace lrhe {
 // Sets the thread-local message returned by lrhe_last_error; returns code.
 int fail(int code, const char* fmt, ...);
 
+// Every device allocation of the library goes through these two, so that an
+// armed allocation fault (environment variable LRHE_FAULT_ALLOC, or
+// lrhe_fault_inject) fails the chosen one with hipErrorOutOfMemory.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t s);
+
 // Records HIP events around a kernel launch on its stream while timing is
 // enabled (lrhe_prof_enable); a no-op otherwise.
 struct ProfScope {

@@ -141,7 +141,9 @@ LRHE_HD void stage_tw(int p, int t, int u, int tau, const TW& tw, uint32_t* w) {
 // [0, 4q); output in [0, 4q).  tw: psi^brv(k) R mod q, k < n.  Each (unit,
 // stage) step reads its twiddles as its butterflies need them; with PF the
 // 2^tau twiddles of the next step are loaded while the current step computes.
-template <class G, bool PF = false, class TW>
+// STRICT keeps every value canonical in [0, q) instead (input and output), for
+// moduli from 2^30 up to 2^31 where 4q no longer fits in 32 bits.
+template <class G, bool PF = false, bool STRICT = false, class TW>
 LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint32_t qinv) {
   const int rr = G::r(p);
   const int nu = G::E >> rr;
@@ -163,13 +165,19 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint3
         if (c & half) continue;
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
-        uint32_t X = umin(*a, *a - q2);
         const uint32_t Tm =
             PF ? mulm(*b, wc[c >> (rr - tau)], q, qinv)
                : tw_mul(tw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))), G::s0(p) == 0, *b,
                         q, qinv);
-        *a = X + Tm;
-        *b = X + q2 - Tm;
+        if constexpr (STRICT) {
+          const uint32_t X = *a, Tc = red1(Tm, q);
+          *a = addm(X, Tc, q);
+          *b = subm(X, Tc, q);
+        } else {
+          const uint32_t X = umin(*a, *a - q2);
+          *a = X + Tm;
+          *b = X + q2 - Tm;
+        }
       }
       LRHE_STAGE_FENCE();
       if constexpr (PF) {
@@ -184,8 +192,8 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint3
 
 // One pass of the inverse (Gentleman-Sande) transform; passes run in the order
 // NPASS-1 .. 0 and stages inside a pass from the last to the first.  Values in
-// and out in [0, 2q).  itw: psi^-brv(k) R mod q.  PF as in fwd_pass.
-template <class G, bool PF = false, class TW>
+// and out in [0, 2q).  itw: psi^-brv(k) R mod q.  PF and STRICT as in fwd_pass.
+template <class G, bool PF = false, bool STRICT = false, class TW>
 LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint32_t qinv) {
   const int rr = G::r(p);
   const int nu = G::E >> rr;
@@ -207,13 +215,20 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint
         if (c & half) continue;
         uint32_t* a = &x[(u << rr) + c];
         uint32_t* b = &x[(u << rr) + c + half];
-        uint32_t U = *a + *b;
-        U = umin(U, U - q2);
-        uint32_t V = *a + q2 - *b;
+        uint32_t U, V;
+        if constexpr (STRICT) {
+          U = addm(*a, *b, q);
+          V = subm(*a, *b, q);
+        } else {
+          U = *a + *b;
+          U = umin(U, U - q2);
+          V = *a + q2 - *b;
+        }
         *a = U;
         *b = PF ? mulm(V, wc[c >> (rr - tau)], q, qinv)
                 : tw_mul(itw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))), G::s0(p) == 0, V,
                          q, qinv);
+        if constexpr (STRICT) *b = red1(*b, q);
       }
       LRHE_STAGE_FENCE();
       if constexpr (PF) {

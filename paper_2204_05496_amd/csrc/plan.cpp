@@ -147,7 +147,7 @@ extern "C" int lrhe_batch_create(lrhe_ctx* c, const lrhe_request* reqs, uint32_t
   const size_t sp = al256(pairs.size() * sizeof(PairDesc)), sg = al256(groups.size() * sizeof(GroupDesc)),
                so = al256(outs.size() * sizeof(OutDesc));
   hipError_t err = hipSetDevice(c->device);
-  if (err == hipSuccess) err = hipMalloc(&b->d_desc, sp + sg + so);
+  if (err == hipSuccess) err = dev_malloc(&b->d_desc, sp + sg + so);
   if (err == hipSuccess) {
     b->d_pairs = (PairDesc*)b->d_desc;
     b->d_groups = (GroupDesc*)((char*)b->d_desc + sp);
@@ -251,7 +251,8 @@ struct SReq {
   uint32_t used_parts = 0;          // groups opened so far
   std::vector<uint32_t> out_g0, out_g1;
   Clock::time_point t_submit, t_done;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;          // recorded after the request's last compression
+  hipEvent_t ready = nullptr;       // recorded on the submitter's stream: inputs written
   int state = 0;                    // 0 queued, 1 scheduled fully, 2 done
 };
 }  // namespace
@@ -332,6 +333,8 @@ void complete_ready(lrhe_server* sv) {   // called with mu held
       arena_free(sv, r->part0, r->nparts);
       if (r->ev) (void)hipEventDestroy(r->ev);
       r->ev = nullptr;
+      if (r->ready) (void)hipEventDestroy(r->ready);
+      r->ready = nullptr;
       sv->inflight.erase(sv->inflight.begin() + k);
       sv->cv.notify_all();
     } else {
@@ -348,6 +351,7 @@ void run_tick(lrhe_server* sv, int slot) {
   std::vector<GroupDesc> groups;
   std::vector<OutDesc> outs;
   std::vector<SReq*> finishing;
+  std::vector<hipEvent_t> waits;    // inputs of requests that start in this tile
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     uint32_t lp = 0;
@@ -359,6 +363,7 @@ void run_tick(lrhe_server* sv, int slot) {
       // a request that would finish here needs room for its output descriptors
       if (r->npairs - r->next <= sv->B - lp && nouts + r->nout > sv->out_cap) break;
       bool open = false;
+      if (r->next == 0 && r->ready) waits.push_back(r->ready);
       while (lp < sv->B && r->next < r->npairs) {
         const uint64_t p = r->next;
         const uint64_t i = p / m->classes, jc = p % m->classes, o = p / n;
@@ -421,7 +426,10 @@ void run_tick(lrhe_server* sv, int slot) {
   memcpy(h, pairs.data(), pairs.size() * sizeof(PairDesc));
   memcpy(h + sp, groups.data(), groups.size() * sizeof(GroupDesc));
   memcpy(h + sp + sg, outs.data(), outs.size() * sizeof(OutDesc));
-  hipError_t err = hipMemcpyAsync(d, h, sv->desc_bytes, hipMemcpyHostToDevice, sv->s);
+  hipError_t err = hipSuccess;
+  for (hipEvent_t w : waits)
+    if (err == hipSuccess) err = hipStreamWaitEvent(sv->s, w, 0);
+  if (err == hipSuccess) err = hipMemcpyAsync(d, h, sv->desc_bytes, hipMemcpyHostToDevice, sv->s);
   const uint32_t tg[2] = {0, (uint32_t)groups.size()};
   char* tb = (char*)sv->d_tile;
   if (err == hipSuccess)
@@ -489,10 +497,10 @@ extern "C" int lrhe_server_create(lrhe_ctx* c, const lrhe_gk* gk, size_t hbm_bud
                    al256((size_t)sv->out_cap * sizeof(OutDesc));
   hipError_t err = hipSetDevice(c->device);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking);
-  if (err == hipSuccess) err = hipMalloc(&sv->d_tile, sv->tw.total);
-  if (err == hipSuccess) err = hipMalloc((void**)&sv->d_part, (size_t)sv->arena_slots * ctb);
+  if (err == hipSuccess) err = dev_malloc(&sv->d_tile, sv->tw.total);
+  if (err == hipSuccess) err = dev_malloc((void**)&sv->d_part, (size_t)sv->arena_slots * ctb);
   for (int k = 0; k < 2 && err == hipSuccess; ++k) {
-    err = hipMalloc(&sv->d_desc[k], sv->desc_bytes);
+    err = dev_malloc(&sv->d_desc[k], sv->desc_bytes);
     if (err == hipSuccess) err = hipHostMalloc(&sv->h_desc[k], sv->desc_bytes, hipHostMallocDefault);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&sv->slot_ev[k], hipEventDisableTiming);
   }
@@ -506,12 +514,12 @@ extern "C" int lrhe_server_create(lrhe_ctx* c, const lrhe_gk* gk, size_t hbm_bud
 }
 
 extern "C" int lrhe_server_submit(lrhe_server* sv, const lrhe_model* m, const uint32_t* xct, uint32_t rows,
-                                  uint32_t* y_out, uint64_t* req_id) {
-  return lrhe_server_submit_keys(sv, nullptr, m, xct, rows, y_out, req_id);
+                                  uint32_t* y_out, void* stream, uint64_t* req_id) {
+  return lrhe_server_submit_keys(sv, nullptr, m, xct, rows, y_out, stream, req_id);
 }
 
 extern "C" int lrhe_server_submit_keys(lrhe_server* sv, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
-                                       uint32_t rows, uint32_t* y_out, uint64_t* req_id) {
+                                       uint32_t rows, uint32_t* y_out, void* stream, uint64_t* req_id) {
   if (!sv || !m || !xct || !y_out || !req_id || rows == 0) return perr(LRHE_EINVAL, "bad argument");
   if (gk && (!gk->d || gk->words != sv->gk->words)) return perr(LRHE_EINVAL, "Galois keys of another context");
   const uint64_t n = sv->c->n;
@@ -526,17 +534,30 @@ extern "C" int lrhe_server_submit_keys(lrhe_server* sv, const lrhe_gk* gk, const
   r->out_g1.assign(r->nout, 0);
   r->nparts = parts_needed(sv, r->npairs, r->nout);
   r->t_submit = Clock::now();
+  // the worker's first tile with this request waits for what the caller queued
+  // on `stream` so far (the encryption that wrote xct, typically)
+  hipError_t herr = hipSetDevice(sv->c->device);
+  if (herr == hipSuccess) herr = hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+  if (herr == hipSuccess) herr = hipEventRecord(r->ready, (hipStream_t)stream);
+  auto drop = [&]() {
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    delete r;
+  };
+  if (herr != hipSuccess) {
+    drop();
+    return perr(LRHE_EDEVICE, "submit: %s", hipGetErrorString(herr));
+  }
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->error) {
-    delete r;
+    drop();
     return perr(sv->error, "server stopped: %s", sv->error_msg.c_str());
   }
   if (r->nparts > sv->arena_slots) {
-    delete r;
+    drop();
     return perr(LRHE_EINVAL, "request needs %u partial slots, the budget holds %u", r->nparts, sv->arena_slots);
   }
   if (!arena_alloc(sv, r->nparts, &r->part0)) {
-    delete r;
+    drop();
     return perr(LRHE_EAGAIN, "admission refused: partial-sum budget in use");
   }
   r->id = sv->next_id++;
@@ -559,6 +580,17 @@ extern "C" int lrhe_server_poll(lrhe_server* sv, uint64_t req_id, int* done, dou
   return LRHE_OK;
 }
 
+extern "C" int lrhe_server_release(lrhe_server* sv, uint64_t req_id) {
+  if (!sv) return perr(LRHE_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(req_id);
+  if (it == sv->reqs.end()) return perr(LRHE_EINVAL, "unknown request %llu", (unsigned long long)req_id);
+  if (it->second->state != 2) return perr(LRHE_EINVAL, "request %llu is not done", (unsigned long long)req_id);
+  delete it->second;
+  sv->reqs.erase(it);
+  return LRHE_OK;
+}
+
 extern "C" int lrhe_server_drain(lrhe_server* sv) {
   if (!sv) return perr(LRHE_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -568,7 +600,7 @@ extern "C" int lrhe_server_drain(lrhe_server* sv) {
 }
 
 extern "C" int lrhe_server_stats(lrhe_server* sv, uint64_t* ticks, uint64_t* pairs, uint32_t* free_slots,
-                                 uint32_t* tile) {
+                                 uint32_t* tile, uint32_t* held) {
   if (!sv) return perr(LRHE_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(sv->mu);
   if (ticks) *ticks = sv->ticks;
@@ -579,6 +611,7 @@ extern "C" int lrhe_server_stats(lrhe_server* sv, uint64_t* ticks, uint64_t* pai
     *free_slots = f;
   }
   if (tile) *tile = sv->B;
+  if (held) *held = (uint32_t)sv->reqs.size();
   return LRHE_OK;
 }
 
@@ -595,6 +628,7 @@ extern "C" void lrhe_server_destroy(lrhe_server* sv) {
   if (sv->s) (void)hipStreamSynchronize(sv->s);
   for (auto& kv : sv->reqs) {
     if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete kv.second;
   }
   for (int k = 0; k < 2; ++k) {

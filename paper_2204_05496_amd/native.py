@@ -16,6 +16,7 @@ LIBPATH = os.path.join(HERE, "liblrhe.so")
 
 LRHE_OK, LRHE_EINVAL, LRHE_EPARAM, LRHE_ENOMEM, LRHE_EAGAIN, LRHE_EDEVICE, LRHE_ENOISE = 0, -1, -2, -3, -4, -5, -6
 WS_ENCRYPT_ROWS, WS_ENCRYPT_COLS, WS_MATMUL_FAST, WS_MATMUL_STANDARD = 1, 2, 3, 4
+CT_HOST = 1   # decryption flag: the ciphertexts are in host memory
 # variants of the key-switch inner-product kernel behind the "mac_mode" tuning key;
 # MAC_MODE_HALF (digit halves on two workgroups per item) is a small-tile choice only
 MAC_MODES = 5
@@ -62,6 +63,10 @@ SIGNATURES = {
     "lrhe_matmul_standard": (i32, [vp, vp, vp, vp, vp, sz, vp]),
     "lrhe_decrypt_slots": (i32, [vp, vp, vp, u32, vp, vp, vp]),
     "lrhe_decrypt_slots_host": (i32, [vp, vp, vp, u32, vp, vp]),
+    "lrhe_decrypt_scores": (i32, [vp, vp, vp, u32, u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]),
+    "lrhe_decrypt_scores_standard": (i32, [vp, vp, vp, u32, u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]),
+    "lrhe_decrypt_check": (i32, [vp, vp, vp, u32, vp, u32, vp, ctypes.POINTER(u64), vp]),
+    "lrhe_fault_inject": (i64, [i64]),
     "lrhe_host_transform": (i32, [vp, u32, vp, i32]),
     "lrhe_to_coeff": (i32, [vp, vp, u64, vp, vp]),
     "lrhe_pk_export": (i32, [vp, vp, vp]),
@@ -74,11 +79,13 @@ SIGNATURES = {
     "lrhe_batch_capture": (i32, [vp, vp, vp, vp, sz, vp]),
     "lrhe_batch_destroy": (None, [vp]),
     "lrhe_server_create": (i32, [vp, vp, sz, ctypes.POINTER(vp)]),
-    "lrhe_server_submit": (i32, [vp, vp, vp, u32, vp, ctypes.POINTER(u64)]),
-    "lrhe_server_submit_keys": (i32, [vp, vp, vp, vp, u32, vp, ctypes.POINTER(u64)]),
+    "lrhe_server_submit": (i32, [vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64)]),
+    "lrhe_server_submit_keys": (i32, [vp, vp, vp, vp, u32, vp, vp, ctypes.POINTER(u64)]),
+    "lrhe_server_release": (i32, [vp, u64]),
     "lrhe_server_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
     "lrhe_server_drain": (i32, [vp]),
-    "lrhe_server_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+    "lrhe_server_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                ctypes.POINTER(u32)]),
     "lrhe_server_destroy": (None, [vp]),
     "lrhe_tune_set": (i32, [vp, ctypes.c_char_p, i32]),
     "lrhe_tune_get": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(i32)]),

@@ -241,3 +241,105 @@ def test_two_clients_batch_and_server(P, torch):
         S, budget = ctx.scores_fast(keys, y, wl.rows, wl.classes)
         assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t)) and budget > 0
     srv.close()
+
+
+# ------------------------------------------------------------------ n = 16384, outputs against the oracle
+UNEVEN_FILE = "uneven_small_n16k_outputs.txt"
+
+
+@pytest.fixture(scope="module")
+def uneven16(P, torch):
+    """Eight requests shaped like the uneven-batching workload (features ~
+    U{10,000..40,000}, 1-4 individuals), encrypted as tests/golden/make_golden.py
+    encrypted them for the oracle."""
+    import golden_ref
+    p = WL.PARAMS["n16k"]
+    ctx = P.Context.from_params(p, device=0)
+    keys = ctx.keygen(2024)
+    specs = WL.uneven_requests(count=8, seed=WL.BASE_SEED + 6, max_rows=4)
+    models = {}
+    reqs = []
+    for r, wl in enumerate(specs):
+        if wl.f not in models:
+            models[wl.f] = ctx.model(wl.W, wl.b)
+        xct = ctx.encrypt_rows(keys, wl.X, seed=600 + r)
+        reqs.append((wl, xct, models[wl.f]))
+    ref = golden_ref.load(UNEVEN_FILE)
+    names = [f"req{r}_{wl.rows}x{wl.f}" for r, wl in enumerate(specs)]
+    assert set(names) == set(ref)
+    return p, ctx, keys, reqs, [ref[nm] for nm in names]
+
+
+def _check_golden(ctx, y, ref, what):
+    import golden_ref
+    bad = golden_ref.mismatches(coeff(ctx, y), ref)
+    assert not bad, f"{what}: {len(bad)} limbs differ from the oracle, first {bad[0][:3]}"
+
+
+def test_uneven_n16k_alone_and_batch_vs_oracle(uneven16, P, torch):
+    """Each of the eight requests alone, then all eight in one planned batch
+    (tiles shared across requests) and its graph replay: every output ciphertext
+    equals the oracle's, bit for bit."""
+    p, ctx, keys, reqs, refs = uneven16
+    for k, (wl, xct, model) in enumerate(reqs):
+        say("alone", k, wl.rows, wl.f)
+        _check_golden(ctx, ctx.matmul_fast(keys, model, xct, wl.rows), refs[k], f"alone {k}")
+    keep = ctx.tune_get("tile")
+    ctx.tune_set("tile", 96)      # 384 pairs in 4 tiles: requests straddle tiles
+    try:
+        ys = [ctx.empty_ct(1) for _ in reqs]
+        b = P.Batch(ctx, keys, [(xct, wl.rows, model, y) for (wl, xct, model), y in zip(reqs, ys)])
+        say("batch", b.npairs, "pairs, tile", b.tile)
+        b.run()
+        torch.cuda.synchronize()
+        for k, y in enumerate(ys):
+            _check_golden(ctx, y, refs[k], f"batch {k}")
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            b.capture(side)
+        side.synchronize()
+        for rep in range(2):
+            for y in ys:
+                y.fill_(0)
+            torch.cuda.synchronize()
+            b.run()
+            torch.cuda.synchronize()
+            for k, y in enumerate(ys):
+                _check_golden(ctx, y, refs[k], f"replay {rep} request {k}")
+        del b
+    finally:
+        ctx.tune_set("tile", keep)
+
+
+def test_uneven_n16k_server_vs_oracle(uneven16, P, torch):
+    """The eight requests through the continuous-batching server, submitted one
+    by one while earlier ones are still on the GPU (small tiles, so a request
+    spans several ticks): every output equals the oracle's, and scores decrypt
+    to X W + b mod t."""
+    p, ctx, keys, reqs, refs = uneven16
+    keep = ctx.tune_get("tile")
+    ctx.tune_set("tile", 32)
+    try:
+        srv = P.Server(ctx, keys, hbm_budget=1 << 30)
+        ys, ids, overlapped = [], [], 0
+        for k, (wl, xct, model) in enumerate(reqs):
+            y = ctx.empty_ct(1)
+            ys.append(y)
+            # a request submitted while an earlier one has not finished joins the running mix
+            overlapped += any(not srv.poll(i)[0] for i in ids)
+            ids.append(srv.submit(model, xct, wl.rows, y))
+            assert ids[-1] is not None
+            time.sleep(0.003)
+        srv.drain()
+        say("server ticks", srv.stats()["ticks"], "submitted while others ran:", overlapped)
+        assert overlapped >= 1
+        for k, (wl, xct, model) in enumerate(reqs):
+            assert srv.poll(ids[k])[0]
+            _check_golden(ctx, ys[k], refs[k], f"server {k}")
+            S, budget = ctx.scores_fast(keys, ys[k], wl.rows, wl.classes)
+            assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t)) and budget > 50
+            srv.release(ids[k])
+        assert srv.stats()["held"] == 0
+        srv.close()
+    finally:
+        ctx.tune_set("tile", keep)

@@ -213,8 +213,10 @@ def test_single_40k_standard(n16k, torch):
 
 def test_batch_512x40k_launch_config(n16k, torch):
     """512 individuals x 40,000 features (the throughput workload) in the launch
-    configuration the benchmark times: scores equal the plain matmul, and
-    sampled pairs equal the oracle pair by pair."""
+    configuration the benchmark times: the whole output ciphertext equals the
+    oracle's (stored by tests/golden/make_golden.py, compared limb by limb),
+    scores equal the plain matmul, and sampled pairs equal the oracle pair by pair."""
+    import golden_ref
     wl = WL.batch()
     ctx, o = n16k.ctx, n16k.o
     say("batch encrypt")
@@ -223,6 +225,9 @@ def test_batch_512x40k_launch_config(n16k, torch):
     say("batch fast")
     y = ctx.matmul_fast(n16k.keys, model, xct, wl.rows)
     torch.cuda.synchronize()
+    ref = golden_ref.load("batch_512x40000x16_fast_output.txt")[wl.name]
+    bad = golden_ref.mismatches(n16k.coeff(y), ref)
+    assert not bad, f"{len(bad)} limbs differ from the oracle, first {bad[0][:3]}"
     say("batch decrypt")
     S, budget = ctx.scores_fast(n16k.keys, y, wl.rows, wl.classes)
     plain = O.plain_scores(wl.X, wl.W, wl.b, n16k.p.t)
