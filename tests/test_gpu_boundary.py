@@ -5,6 +5,7 @@ server submission ordered by a producer stream, and the release of finished
 server requests.  No test makes a kernel fail: every fault is injected on the
 host before any launch."""
 import ctypes
+import gc
 import sys
 import time
 
@@ -148,6 +149,7 @@ def test_server_release_returns_memory(tiny3, P, torch):
     wl = WL.tiny(params="tiny3")
     model = ctx.model(wl.W, wl.b)
     srv = P.Server(ctx, keys, hbm_budget=256 << 20)
+    gc.collect()                                   # leftovers of earlier tests
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     for round_ in range(3):
@@ -164,6 +166,7 @@ def test_server_release_returns_memory(tiny3, P, torch):
         with pytest.raises(P.native.LrheError):
             srv.poll(ids[0])                       # forgotten
         assert srv.stats()["held"] == 0
+        gc.collect()
         torch.cuda.synchronize()
         assert torch.cuda.memory_allocated() == base, round_
     srv.close()
