@@ -27,11 +27,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "encrypted LR inferences/s at 40k features; single-inference ms; NTT HBM GB/s"
-# chip figures (MI355X): 256 CUs at 2.4 GHz, HBM3E 8 TB/s; a Montgomery modular
-# multiply needs two 32x32->64 multiply-adds (64 lanes/clk/CU) and one 32-bit
-# low multiply (32 lanes/clk/CU): 1/16 CU-cycle per lane -> 9.83 T modmul/s
+# chip figures (MI355X): 256 CUs at 2.4 GHz, HBM3E 8 TB/s.  A Montgomery modular
+# multiply issues two v_mad_u64_u32 (48 lanes per clock per CU, measured by
+# lrhe_prof_valu_rate: dependent inline-asm chains) and one v_mul_lo_u32 (64
+# lanes per clock per CU, half of the 128 of a 32-bit add):
+# 2/48 + 1/64 CU-cycles per lane -> 10.72 T modmul/s
 HBM_PEAK_GBPS = 8000.0
-MODMUL_PEAK_T = 256 * 2.4e9 * 16 / 1e12
+CU_CLOCKS = 256 * 2.4e9
+MODMUL_PEAK_T = CU_CLOCKS / (2 / 48 + 1 / 64) / 1e12
+VALU_PROBES = ("v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32", "montgomery_butterfly")
+
+
+def valu_rates(lib):
+    """Issue rates measured on this GPU (lane instructions per second; the last
+    entry in butterflies per second), next to the lanes per clock per CU they mean."""
+    out = {}
+    for op, name in enumerate(VALU_PROBES):
+        r, ms = ctypes.c_double(), ctypes.c_double()
+        if lib.lrhe_prof_valu_rate(op, 128, 3, ctypes.byref(r), ctypes.byref(ms)) != 0:
+            return None
+        out[name] = {"T_per_s": round(r.value / 1e12, 2), "per_cu_clock": round(r.value / CU_CLOCKS, 1)}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def log(*a):
@@ -88,24 +114,34 @@ def counted_traffic(le_mac, mac_mode):
 
 
 def cpu_baseline(pname, rows, f, classes, seed):
-    """The oracle as it stands, on a bounded sample of the same workload."""
+    """The oracle as it stands, on a bounded sample of the same workload, and on
+    the whole single-individual workload (1 x 40,000 x 16)."""
     from oracle import oracle as O
     import workloads as WL
     p = WL.PARAMS[pname]
-    wl = WL.make("cpu_sample", pname, rows, f, classes, 0.01, seed)
     o = O.Oracle(p.n, list(p.q), p.P, p.t)
     ko = o.keygen(2024)
-    wpt = o.encode_weights(wl.W)
-    t0 = time.perf_counter()
-    xo = o.encrypt_rows(ko, wl.X, seed=3)
-    y = o.fast_matmul(ko, xo, wpt, wl.b)
-    S, _ = o.scores_fast(ko, y, rows, classes)
-    dt = time.perf_counter() - t0
-    assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t))
+
+    def run(wl, seed_enc):
+        wpt = o.encode_weights(wl.W)
+        t0 = time.perf_counter()
+        xo = o.encrypt_rows(ko, wl.X, seed=seed_enc)
+        y = o.fast_matmul(ko, xo, wpt, wl.b)
+        S, _ = o.scores_fast(ko, y, wl.rows, wl.classes)
+        dt = time.perf_counter() - t0
+        assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, p.t))
+        return dt
+
+    dt = run(WL.make("cpu_sample", pname, rows, f, classes, 0.01, seed), 3)
+    single = WL.single(f=f)
+    dt1 = run(single, 5)
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     return {"value": rows / dt, "unit": "inferences/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{rows} individuals x {f} features x {classes} classes ({rows * classes} pairs): "
-                      f"encrypt + Algorithm 1 + decrypt, {dt:.1f} s"}
+                      f"encrypt + Algorithm 1 + decrypt, {dt:.1f} s",
+            "single_inference_ms": {"workload": single.name, "fast": round(dt1 * 1e3, 1),
+                                    "step": "encrypt + Algorithm 1 + decrypt, in full"}}
 
 
 def _uneven_inputs(ctx, keys, P, WL, torch, count):
@@ -419,6 +455,9 @@ def main():
                                   "inv": round(nbytes / (msi / ci * 1e-3) / 1e9, 1),
                                   "fwd_avg_ms": round(msf / cf, 3), "inv_avg_ms": round(msi / ci, 3)}
         del buf
+
+    if not args.no_extras:
+        extras["valu_rates"] = valu_rates(lib)
 
     if not args.no_extras and args.uneven:
         extras["uneven_batch"] = bench_uneven(ctx, keys, P, WL, O, torch, args)

@@ -324,6 +324,16 @@ int lrhe_autotune_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model
 void lrhe_prof_enable(int on);
 void lrhe_prof_reset(void);
 int lrhe_prof_get(const char* kernel, uint64_t* launches, double* total_ms);
+/* Issue rate of the vector instructions the transforms are built from, on the
+ * current device: op 0 v_add_u32, 1 v_mul_lo_u32, 2 v_mul_hi_u32,
+ * 3 v_mad_u64_u32 (lane instructions per second, from dependent inline-asm
+ * chains the compiler cannot fold), 4 the Montgomery forward butterfly of the
+ * transforms (butterflies per second).  iters loop iterations of 128
+ * operations per lane on 64 workgroups of 256 lanes per compute unit; the best
+ * of reps timed launches after a warm-up.  best_ms may be NULL.  EINVAL for
+ * other ops or non-positive counts, EDEVICE on a HIP error.  Measurement
+ * only: it backs the ALU peak that kernel throughput is compared against. */
+int lrhe_prof_valu_rate(int op, int iters, int reps, double* per_s, double* best_ms);
 
 /* Allocation fault injection (failure handling tests): the k-th device
  * allocation of the library from now on fails as if out of memory, so the call

@@ -93,6 +93,7 @@ SIGNATURES = {
     "lrhe_prof_enable": (None, [i32]),
     "lrhe_prof_reset": (None, []),
     "lrhe_prof_get": (i32, [ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]),
+    "lrhe_prof_valu_rate": (i32, [i32, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
