@@ -152,6 +152,23 @@ void lrhe_model_destroy(lrhe_model* m);
 int lrhe_matmul_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct,
                      uint32_t rows, uint32_t* y_out, void* ws, size_t ws_bytes, void* stream);
 
+/* lrhe_matmul_fast for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same output bits, with the workspace taken from a
+ * fixed device array of 96 MiB (LRHE_SCRATCH_BYTES in the library) that every
+ * GPU the library runs on holds from the loading of the library until the
+ * process ends; its address is looked up once per device by
+ * lrhe_ctx_create.  The call allocates nothing (no hipMalloc, no library
+ * allocation).  The caller still passes the inputs and y_out.  Jobs whose
+ * workspace (lrhe_workspace_bytes(LRHE_WS_MATMUL_FAST)) exceeds the scratch
+ * are refused with EINVAL: one individual x 16 classes at n = 16384 with 7
+ * data primes needs 81 MiB.  All calls on one GPU share that GPU's array and
+ * nothing is cleared between them (the path writes every scratch word before
+ * reading it), so calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race: order them.  Errors: EINVAL, EDEVICE. */
+int lrhe_matmul_fast_noalloc(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct,
+                             uint32_t rows, uint32_t* y_out, void* stream);
+
 /* Debug/parity variant of lrhe_matmul_fast: runs pairs [pair0, pair0 + npairs)
  * (pair r = i classes + j) through the same kernels and writes each pair's
  * ciphertext after `stage` to pairs_out (npairs ciphertexts):

@@ -246,6 +246,13 @@ class Context:
                                          ws.numel(), _stream()))
         return out
 
+    def matmul_fast_noalloc(self, keys: Keys, model: Model, xct, rows: int, out):
+        """Algorithm 1 with the library's fixed device scratch as workspace (no
+        allocation in the call; out is caller-provided)."""
+        N.check(N.lib().lrhe_matmul_fast_noalloc(self.h, keys.gk, model.handle, N.ptr(xct), rows, N.ptr(out),
+                                                 _stream()))
+        return out
+
     def matmul_fast_pairs(self, keys: Keys, model: Model, xct, rows: int, pair0: int, npairs: int, stage: int,
                           out=None, ws=None):
         out = self.empty_ct(npairs) if out is None else out

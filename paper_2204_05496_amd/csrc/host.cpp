@@ -432,6 +432,9 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
   // upload
   hipError_t err = hipSetDevice(device);
   if (err != hipSuccess) { delete c; return fail(LRHE_EDEVICE, "hipSetDevice(%d): %s", device, hipGetErrorString(err)); }
+  // the device address of the non-allocating path's fixed scratch, once per device
+  err = scratch_resolve(device);
+  if (err != hipSuccess) { delete c; return fail(LRHE_EDEVICE, "scratch on device %d: %s", device, hipGetErrorString(err)); }
   auto up = [&](uint32_t** dst, const std::vector<uint32_t>& src) -> hipError_t {
     hipError_t e2 = dev_malloc((void**)dst, src.size() * 4);
     if (e2 != hipSuccess) return e2;
@@ -1078,6 +1081,25 @@ extern "C" int lrhe_matmul_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_model
   const FastWs lay = fast_ws_layout(c, (uint32_t)npairs, m->classes);
   if (!ws || ws_bytes < lay.total) return fail(LRHE_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, lay.total);
   NEED_DEVICE(c);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_fast(c, gk->d, m, xct, rows, 0, (uint32_t)npairs, -1, y_out, ws, lay, (hipStream_t)stream));
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_matmul_fast_noalloc(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
+                                        uint32_t rows, uint32_t* y_out, void* stream) {
+  if (!c || !gk || !m || !xct || !y_out) return fail(LRHE_EINVAL, "null argument");
+  if (rows == 0) return fail(LRHE_EINVAL, "no rows");
+  const uint64_t npairs = (uint64_t)rows * m->classes;
+  if (npairs > 0xffffffffull) return fail(LRHE_EINVAL, "too many pairs");
+  NEED_DEVICE(c);
+  const FastWs lay = fast_ws_layout(c, (uint32_t)npairs, m->classes);
+  if (lay.total > LRHE_SCRATCH_BYTES)
+    return fail(LRHE_EINVAL, "%llu rows x %u classes need a workspace of %zu bytes, above the fixed scratch of %llu bytes "
+                "of the non-allocating path (use lrhe_matmul_fast with a caller workspace)",
+                (unsigned long long)rows, m->classes, lay.total, (unsigned long long)LRHE_SCRATCH_BYTES);
+  void* ws = scratch_ptr(c->device);
+  if (!ws) return fail(LRHE_EDEVICE, "fixed scratch of device %d not resolved", c->device);
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(launch_fast(c, gk->d, m, xct, rows, 0, (uint32_t)npairs, -1, y_out, ws, lay, (hipStream_t)stream));
   return LRHE_OK;

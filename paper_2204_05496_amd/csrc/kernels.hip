@@ -2,6 +2,8 @@
 // encoding, encryption, model encoding, Algorithm 1 tiles, standard baseline).
 // The key-switch steps and the mask are launched through launch_ks_step /
 // launch_mask_step, instantiated per ring dimension in ks_step.hip.
+#include <mutex>
+
 #include "kernels_dev.h"
 
 namespace lrhe {
@@ -177,12 +179,48 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
   const uint32_t most = max(npairs, max(ngroups, nouts));
   k_plan_single<<<blocks_for(most, 256), 256, 0, s>>>(c->dc, xct, m->wpt, m->dbias, m->K, m->classes, pair0, npairs,
                                                       lay.B, lay.G, out, pairs, groups, ngroups, outs, nouts);
-  std::vector<uint32_t> tile_g0;
-  for (uint32_t pb = 0; pb < npairs; pb += lay.B) tile_g0.push_back(pb / lay.G);
-  tile_g0.push_back(ngroups);
-  return launch_plan(c, gk_d, pairs, npairs, groups, tile_g0.data(), lay.B, outs, nouts, stage, out,
+  // first group of every tile; jobs of up to 64 tiles keep the list on the stack
+  const uint32_t ntiles = (npairs + lay.B - 1) / lay.B;
+  uint32_t few[65];
+  std::vector<uint32_t> many;
+  uint32_t* tile_g0 = few;
+  if (ntiles + 1 > 65) {
+    many.resize(ntiles + 1);
+    tile_g0 = many.data();
+  }
+  for (uint32_t t = 0; t < ntiles; ++t) tile_g0[t] = t * lay.B / lay.G;
+  tile_g0[ntiles] = ngroups;
+  return launch_plan(c, gk_d, pairs, npairs, groups, tile_g0, lay.B, outs, nouts, stage, out,
                      (uint32_t*)(base + lay.cA), (uint32_t*)(base + lay.cB), (uint32_t*)(base + lay.D),
                      (uint32_t*)(base + lay.ACC), lay.acc_slots, (uint32_t*)(base + lay.part), s);
+}
+
+// ------------------------------------------------------------------ fixed scratch
+// Workspace of lrhe_matmul_fast_noalloc: a file-scope device array that every
+// GPU the library runs on holds from the loading of the code object until the
+// process ends.  In host code its name is only a stand-in; the device address
+// is looked up once per device (at context creation, with the device current)
+// and every host-side use goes through that address.
+static __device__ __align__(256) unsigned char scratch[LRHE_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch[LRHE_MAX_DEVICES];
+
+hipError_t scratch_resolve(int device) {
+  if (device < 0 || device >= LRHE_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= LRHE_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
 }
 
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,

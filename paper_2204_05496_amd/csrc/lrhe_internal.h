@@ -13,6 +13,10 @@
 #define LRHE_MAXL 15
 #define LRHE_MINLOGN 10
 #define LRHE_MAXLOGN 15
+// the fixed workspace of lrhe_matmul_fast_noalloc (bytes, per device): one
+// individual x 16 classes at n = 16384 with 7 data primes needs 81 MiB
+#define LRHE_SCRATCH_BYTES (96ull << 20)
+#define LRHE_MAX_DEVICES 64
 
 namespace lrhe {
 
@@ -204,4 +208,8 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
                        uint32_t* ACC, uint64_t acc_slots, uint32_t* part, hipStream_t s);
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,
                            hipStream_t s);
+// device address of the fixed scratch array on a device: resolved once per
+// device (with that device current) by scratch_resolve, nullptr before
+hipError_t scratch_resolve(int device);
+void* scratch_ptr(int device);
 }  // namespace lrhe
