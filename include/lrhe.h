@@ -313,7 +313,11 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * order), the special-prime inverse transforms in a kernel of their own
  * and the division by P split by ciphertext part (more workgroups for tiles
  * too small to fill the GPU; small class only, EINVAL for the large class or
- * a bare key).  These five keys exist in two classes, for tiles of fewer than
+ * a bare key); "fuse_intt" = 1 lets the rounded division by P of each
+ * rotation step also compute the next step's digits (inverse transform of the
+ * automorphism of c1), so the digit kernel runs on the first step only; 0
+ * (default) runs it on every step; ignored by variant 4.  These six keys exist
+ * in two classes, for tiles of fewer than
  * "small_below" pairs (default 64; such launches are latency-bound) and for
  * larger tiles: "small.<key>" and "large.<key>" address one class, a bare key
  * sets both and reads the large class.  Defaults: large tiles le_intt 5,

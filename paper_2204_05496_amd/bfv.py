@@ -275,7 +275,7 @@ class Context:
         return v.value
 
     def tuning(self) -> dict:
-        names = ("le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode")
+        names = ("le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt")
         return {"large": {k: self.tune_get("large." + k) for k in names},
                 "small": {k: self.tune_get("small." + k) for k in names},
                 "tile": self.tune_get("tile"), "small_below": self.tune_get("small_below")}

@@ -1173,6 +1173,7 @@ static int* knob_field(lrhe::Knobs* kn, const std::string& k) {
   if (k == "le_moddown") return &kn->le_moddown;
   if (k == "le_mask") return &kn->le_mask;
   if (k == "mac_mode") return &kn->mac_mode;
+  if (k == "fuse_intt") return &kn->fuse_intt;
   return nullptr;
 }
 
@@ -1193,6 +1194,8 @@ extern "C" int lrhe_tune_set(lrhe_ctx* c, const char* key, int value) {
     if (value == LRHE_MAC_MODE_HALF && kn != &c->tune.small)
       return fail(LRHE_EINVAL, "mac_mode %d is a choice of the small-tile class only (small.mac_mode)",
                   LRHE_MAC_MODE_HALF);
+  } else if (k == "fuse_intt") {
+    if (value != 0 && value != 1) return fail(LRHE_EINVAL, "fuse_intt must be 0 or 1");
   } else if (!le_valid(c->logn, value)) {
     return fail(LRHE_EINVAL, "%s = %d not available at n = %u", key, value, c->n);
   }
@@ -1272,7 +1275,9 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
           }
       }
       mac_ms[le - 4][mode] = ms[3];
-      if (mode == LRHE_MAC_MODE_HALF) half_ms[le - 4] = ms[3] + ms[4] + ms[1];
+      // the digit-halves variant runs k_ks_intt on every step (the others on
+      // the first only, when k_ks_moddown writes the next step's digits)
+      if (mode == LRHE_MAC_MODE_HALF) half_ms[le - 4] = ms[3] + ms[4] + ms[1] + ms[0];
     }
   }
   for (int k = 0; k < 3; ++k) *knobs[k] = best_le[k];
@@ -1280,7 +1285,8 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   int best_mac_le = K.le_mac, best_mode = 0;
   for (int le = 4; le <= 6; ++le)
     for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
-      const double cost = mode == LRHE_MAC_MODE_HALF ? half_ms[le - 4] : mac_ms[le - 4][mode] + best_ms[1];
+      const double cost =
+          mode == LRHE_MAC_MODE_HALF ? half_ms[le - 4] : mac_ms[le - 4][mode] + best_ms[1] + best_ms[0];
       if (cost < best) {
         best = cost;
         best_mac_le = le;

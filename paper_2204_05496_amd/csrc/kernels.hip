@@ -139,9 +139,13 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
       continue;
     }
     const int steps = (stage >= 2 && stage < 100) ? stage - 2 : (int)c->ngal;
+    // digits of step gi + 1 from step gi's division by P where the variant allows
+    const bool fuse = kn.fuse_intt && kn.mac_mode != LRHE_MAC_MODE_HALF;
     for (int gi = 0; gi < steps; ++gi) {
       hipError_t e = hipErrorInvalidValue;
-      LRHE_DISPATCH(c->logn, e = launch_ks_step<LN>(c, kn, tp, gk_d, Bt, (uint32_t)gi, cur, D, ACC, acc_slots, nxt, s));
+      const bool d_ready = fuse && gi > 0, d_next = fuse && gi + 1 < steps;
+      LRHE_DISPATCH(c->logn, e = launch_ks_step<LN>(c, kn, tp, gk_d, Bt, (uint32_t)gi, cur, D, ACC, acc_slots, nxt,
+                                                    d_ready, d_next, s));
       if (e != hipSuccess) return e;
       uint32_t* tmp = cur;
       cur = nxt;

@@ -125,8 +125,8 @@ __device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t
 }
 
 // forward transform: x in pass-0 layout with values < 4q; returns the
-// evaluations in last-pass layout, canonical [0, q)
-template <class G, bool DB = false, bool PF = false, class TW = TwView>
+// evaluations in last-pass layout, canonical [0, q) (LAZY: left in [0, 4q))
+template <class G, bool DB = false, bool PF = false, class TW = TwView, bool LAZY = false>
 __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TW& tw, const Mod& m, int t,
                                         int* par = nullptr) {
 #pragma unroll
@@ -134,8 +134,10 @@ __device__ __forceinline__ void ntt_fwd(uint32_t* x, uint32_t* lds, const TW& tw
     if (p > 0) xchg<G, DB>(lds, p - 1, p, x, t, par);
     fwd_pass<G, PF>(p, t, x, tw, m.q, m.qinv);
   }
+  if constexpr (!LAZY) {
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = red2(x[e], m.q);
+    for (int e = 0; e < G::E; ++e) x[e] = red2(x[e], m.q);
+  }
 }
 
 // inverse transform: x in last-pass layout with values < 2q (canonical with
@@ -590,7 +592,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
 #pragma unroll
         for (int e = 0; e < G::E; ++e) x[e] = dp.at(tb, (uint32_t)i * G::N + G::eoff(0, e));
       }
-      ntt_fwd<G, DB, PF>(x, lds, tw, mr, tid_fresh(), &par);
+      // the products reduce any input below 2^32, so the digit stays lazy in
+      // [0, 4 q_r) unless it feeds the unreduced 64-bit sums
+      ntt_fwd<G, DB, PF, TwView, !A64>(x, lds, tw, mr, tid_fresh(), &par);
     }
     // keep the key loads below the transform: hoisting them into it costs 64 VGPRs
     __builtin_amdgcn_sched_barrier(0);
@@ -733,11 +737,15 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown_part(DevCtx 
 // key switch, part 3: rounded division by P, coefficient-wise
 // round(acc / P) = (acc - [acc]_P) / P with [acc]_P the centred residue
 // rho_x - h, so out_x = (acc_x - NTT(rho_x - h)) P^-1 mod q_j; then the
-// rotate-and-accumulate c0' = c0 + sigma_g(c0) + out_b, c1' = c1 + out_a
+// rotate-and-accumulate c0' = c0 + sigma_g(c0) + out_b, c1' = c1 + out_a.
+// With gnext != 0 the workgroup also does part 1 of the next step for its
+// limb: Dn_j = INTT(sigma_gnext(c1'_j)), from the c1' limb it holds (the
+// permutation through LDS, as in k_ks_intt), which saves reading c1' again.
 template <int LOGN, int LE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, const uint32_t* __restrict__ cin,
                                                                    const uint32_t* __restrict__ ACC, uint32_t g,
-                                                                   uint32_t* __restrict__ cout) {
+                                                                   uint32_t* __restrict__ cout, uint32_t gnext,
+                                                                   uint32_t* __restrict__ Dn) {
   using G = Geom<LOGN, LE>;
   const int t = threadIdx.x;
   __shared__ uint32_t lds[G::LDS_WORDS];
@@ -786,6 +794,25 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
     x[e] = addm(cc[e], oa, md.q);
   }
   storeL<G>(DBuf(cout + (lp * 2 * L + L + j) * G::N, G::N), x, t);
+  if (gnext) {
+    // c1'_j to LDS at its natural positions (the transform's last exchange
+    // has been read by every thread once all pass the barrier), then gathered
+    // through the next automorphism into the last-pass layout
+    // (addresses from a fresh thread id, so that none is computed early and
+    // kept live through the two transforms above)
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    const uint32_t bw = G::tbase(G::NPASS - 1, tid_fresh());
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) lds[G::pad(bw + G::eoff(G::NPASS - 1, e))] = x[e];
+    __syncthreads();
+    const uint32_t br = G::tbase(G::NPASS - 1, tid_fresh());
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(br + G::eoff(G::NPASS - 1, e), gnext, LOGN))];
+    const int tf = tid_fresh();
+    ntt_inv<G>(x, lds, twv(c.itw, j, G::N), md, tf);
+    store0<G>(DBuf(Dn + (lp * L + j) * G::N, G::N), x, tf);
+  }
 }
 
 // bias + one-hot mask of each pair of a group, the group's masked ciphertexts

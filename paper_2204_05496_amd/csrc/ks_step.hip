@@ -38,7 +38,7 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
 template <int LN>
 hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp, const uint32_t* gk_d, uint32_t Bt,
                           uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint64_t acc_slots,
-                          uint32_t* nxt, hipStream_t s) {
+                          uint32_t* nxt, bool d_ready, bool d_next, hipStream_t s) {
   const uint32_t L = c->L, g = c->gal[gi];
   // the digit-halves variant keeps a second accumulator per item, ACC2, in the
   // slots after the tile's own
@@ -48,7 +48,9 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
     if (2ull * Bt > acc_slots) return hipErrorInvalidValue;
     ACC2 = ACC + (uint64_t)Bt * (L + 1) * 2 * c->n;
   }
-  {
+  // the digits of this step: from k_ks_intt, or already written by the
+  // previous step's k_ks_moddown (d_ready)
+  if (!d_ready) {
     ProfScope ps(s, "k_ks_intt");
     LRHE_LE_SWITCH(kn.le_intt, {
       k_ks_intt<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, g, D);
@@ -76,9 +78,12 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
       k_ks_moddown_part<LN, LE><<<(unsigned)(Bt * L * 2), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, ACC2, g, nxt);
     });
   } else {
+    // d_next: the digits of step gi + 1 come out of this k_ks_moddown
+    if (d_next && gi + 1 >= c->ngal) return hipErrorInvalidValue;
+    const uint32_t gn = d_next ? c->gal[gi + 1] : 0;
     ProfScope ps(s, "k_ks_moddown");
     LRHE_LE_SWITCH(kn.le_moddown, {
-      k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt);
+      k_ks_moddown<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, ACC, g, nxt, gn, D);
     });
   }
   return hipGetLastError();
@@ -96,7 +101,7 @@ hipError_t launch_mask_step(const lrhe_ctx* c, const Knobs& kn, const uint32_t* 
 
 template hipError_t launch_ks_step<LRHE_KS_LOGN>(const lrhe_ctx*, const Knobs&, const PairDesc*, const uint32_t*,
                                                  uint32_t, uint32_t, const uint32_t*, uint32_t*, uint32_t*, uint64_t,
-                                                 uint32_t*, hipStream_t);
+                                                 uint32_t*, bool, bool, hipStream_t);
 template hipError_t launch_mask_step<LRHE_KS_LOGN>(const lrhe_ctx*, const Knobs&, const uint32_t*, const PairDesc*,
                                                    const GroupDesc*, uint32_t, int, uint32_t*, hipStream_t);
 

@@ -84,6 +84,11 @@ namespace lrhe {
 struct Knobs {
   int le_intt = 5, le_mac = 5, le_moddown = 5, le_mask = 5;
   int mac_mode = 0;   // variant of k_ks_mac, 0 .. LRHE_MAC_NMODES - 1
+  // k_ks_moddown also writes the next step's digits (no k_ks_intt after the
+  // first step); not with the digit-halves variant, whose division by P is
+  // split.  Off by default: at 512 x 40,000 the extra inverse transform costs
+  // k_ks_moddown more (3.51 -> 4.89 ms) than k_ks_intt takes (1.2 ms)
+  int fuse_intt = 0;
 };
 // Tiles below small_below pairs (latency-bound: fewer workgroups than the chip
 // holds) and larger tiles (throughput-bound) keep separate choices.
@@ -198,7 +203,7 @@ hipError_t launch_fast(const lrhe_ctx* c, const uint32_t* gk_d, const lrhe_model
 template <int LN>
 hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp, const uint32_t* gk_d, uint32_t Bt,
                           uint32_t gi, const uint32_t* cur, uint32_t* D, uint32_t* ACC, uint64_t acc_slots,
-                          uint32_t* nxt, hipStream_t s);
+                          uint32_t* nxt, bool d_ready, bool d_next, hipStream_t s);
 template <int LN>
 hipError_t launch_mask_step(const lrhe_ctx* c, const Knobs& kn, const uint32_t* cur, const PairDesc* tp,
                             const GroupDesc* tg, uint32_t ngt, int mode, uint32_t* dst, hipStream_t s);

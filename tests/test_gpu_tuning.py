@@ -88,14 +88,15 @@ def test_every_tuning_choice_same_bits(P, torch, pname, rows, f, classes):
         assert np.array_equal(to_numpy_u32(ctx.to_coeff(ref)).astype(np.uint64), exp)
     les = valid_les(ctx)
     say(pname, "valid residues-per-thread", les)
-    for le, mode in itertools.product(les, range(P.native.MAC_MODES)):
+    for le, mode, fuse in itertools.product(les, range(P.native.MAC_MODES), (0, 1)):
         for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
             ctx.tune_set(knob, le)
         ctx.tune_set("small.mac_mode", mode)   # every tile of these jobs is in the small class
-        say(pname, "le", le, "mac_mode", mode)
+        ctx.tune_set("fuse_intt", fuse)
+        say(pname, "le", le, "mac_mode", mode, "fuse_intt", fuse)
         y = ctx.matmul_fast(keys, model, xct, rows)
         torch.cuda.synchronize()
-        assert torch.equal(y, ref), f"le {le} mac_mode {mode}"
+        assert torch.equal(y, ref), f"le {le} mac_mode {mode} fuse_intt {fuse}"
     for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
         ctx.tune_set(knob, 5)
     ctx.tune_set("mac_mode", 0)
