@@ -323,6 +323,36 @@ def plain_scores(X: np.ndarray, W: np.ndarray, bias, t: int) -> np.ndarray:
     return np.where(S > (t - 1) // 2, S - t, S)
 
 
+def fixed_point(a, bits: int) -> np.ndarray:
+    """The paper's fixed-point conversion (section "Private inference
+    protocol"): a value is multiplied by 2^bits and taken to the nearest
+    integer (ties to even), int64."""
+    return np.rint(np.asarray(a, dtype=np.float64) * float(2 ** bits)).astype(np.int64)
+
+
+def plain_fixed_scores(Xs: np.ndarray, Ws: np.ndarray, bs) -> np.ndarray:
+    """The exact integer result of the scaled computation, X_s W_s + b_s, with
+    no reduction (it is what the CRT pair must give back); Python integers."""
+    S = np.asarray(Xs, dtype=object) @ np.asarray(Ws, dtype=object) + np.asarray(bs, dtype=object)[None, :]
+    return S
+
+
+def crt_pair(r0, r1, t0: int, t1: int) -> np.ndarray:
+    """The integer z in (-t0 t1 / 2, t0 t1 / 2] with z = r0 mod t0 and z = r1 mod
+    t1 (the Chinese remainder theorem over the paper's plaintext pair), for
+    arrays of residues (any representatives); Python integers."""
+    M = t0 * t1
+    inv = pow(t0, -1, t1)
+    r0 = np.asarray(r0, dtype=object)
+    r1 = np.asarray(r1, dtype=object)
+    out = np.empty(r0.shape, dtype=object)
+    for idx in np.ndindex(r0.shape):
+        a, b = int(r0[idx]) % t0, int(r1[idx]) % t1
+        z = a + t0 * (((b - a) * inv) % t1)
+        out[idx] = z - M if z > M // 2 else z
+    return out
+
+
 def argmax_lowest(S: np.ndarray) -> np.ndarray:
     """Predicted class = argmax_j score (section "Approximation of non-linear
     function in private inference"); ties go to the lowest class index."""

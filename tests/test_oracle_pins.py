@@ -252,7 +252,7 @@ def test_automorphisms_rotate_rows(o16):
 
 
 # ---------------------------------------------------------------- BFV constants and keys
-@pytest.mark.parametrize("pname", ["tiny", "tiny3", "n16k"])
+@pytest.mark.parametrize("pname", ["tiny", "tiny3", "n16k", "paper_t0", "paper_t1"])
 def test_delta_constants(pname):
     p = WL.PARAMS[pname]
     o = O.Oracle(p.n, list(p.q), p.P, p.t)
@@ -522,3 +522,82 @@ def test_standard_scalar_centred_lift_bruteforce(o16):
                         acc[0] += (Q * bt + t // 2) // t      # Delta(b_j) = round(Q b / t) on coefficient 0
                     ok &= [v % qj for v in acc] == [int(v) for v in out[j, x, li]]
         assert ok == centred
+
+
+# ---------------------------------------------------------------- the paper's precision point
+def test_paper_precision_arithmetic():
+    """Section "Private inference protocol": t0 = 1073872897 (30 bits) and t1 =
+    114689 (16 bits) are primes that batch at n = 8192 (both 1 mod 2n); t1 does
+    not at n = 16384.  Outputs need 8 + s_x + s_w + ceil(log2 f) = 44 bits at
+    f = 40,960, within the signed range of t0 t1 (about 2^45.8)."""
+    from bruteforce import is_prime
+    t0, t1 = WL.T_PAIR
+    assert (t0, t1) == (1073872897, 114689) and is_prime(t0) and is_prime(t1)
+    assert t0 % 16384 == 1 and t1 % 16384 == 1 and t1 % 32768 != 1
+    assert 29 < math.log2(t0) < 30.01 and 16 < math.log2(t1) < 17
+    need = 8 + WL.S_X + WL.S_W + math.ceil(math.log2(40960))
+    assert need == 44 and 2 ** need < (t0 * t1) // 2
+
+
+def test_crt_pair_bruteforce():
+    """crt_pair returns the unique integer of (-t0 t1 / 2, t0 t1 / 2] with the
+    given residues: checked on integers drawn over the whole range and at its
+    edges, with residues given in [0, t) and centred."""
+    t0, t1 = WL.T_PAIR
+    M = t0 * t1
+    half = M // 2
+    r = rng(11)
+    zs = [0, 1, -1, half, -half + 1, half - 1, -half + 2, t0, -t0, t1, -t1, t0 * 7, 2 ** 44, -(2 ** 44)]
+    zs += [int(v) for v in r.integers(-half + 1, half + 1, size=200, dtype=np.int64)]
+    r0 = np.array([z % t0 for z in zs], dtype=object)
+    r1 = np.array([z % t1 for z in zs], dtype=object)
+    assert list(O.crt_pair(r0, r1, t0, t1)) == zs
+    c0 = np.array([v - t0 if v > (t0 - 1) // 2 else v for v in r0], dtype=object)
+    c1 = np.array([v - t1 if v > (t1 - 1) // 2 else v for v in r1], dtype=object)
+    assert list(O.crt_pair(c0, c1, t0, t1)) == zs
+    # brute force on small coprime moduli: every residue pair, against a search
+    for a, b in ((5, 7), (7, 12), (9, 4)):
+        for x in range(a):
+            for y in range(b):
+                z = int(O.crt_pair(np.array([x], dtype=object), np.array([y], dtype=object), a, b)[0])
+                cands = [v for v in range(-(a * b) // 2, (a * b) // 2 + 1) if v % a == x and v % b == y
+                         and -(a * b) / 2 < v <= (a * b) / 2]
+                assert [z] == cands
+
+
+def test_fixed_point_closed_forms():
+    """Values that are exact multiples of 2^-s map to the integer itself; halves
+    go to the even neighbour; signs are kept."""
+    for s in (WL.S_X, WL.S_W, WL.S_X + WL.S_W):
+        k = np.array([0, 1, -1, 5, -77, 2 ** 13, -(2 ** 13)], dtype=np.int64)
+        assert np.array_equal(O.fixed_point(k / 2.0 ** s, s), k)
+        assert list(O.fixed_point(np.array([0.5, 1.5, 2.5, -0.5, -1.5]) / 2.0 ** s, s)) == [0, 2, 2, 0, -2]
+        assert list(O.fixed_point(np.array([0.49, 0.51, -0.51]) / 2.0 ** s, s)) == [0, 1, -1]
+
+
+def test_paper_point_oracle_end_to_end():
+    """n = 8192 with the CRT pair: Algorithm 1 run once per plaintext modulus (each
+    under its own keys) decrypts, after recombination, to exactly X_s W_s + b_s,
+    the scaled integer result, which exceeds t0 (so neither modulus alone holds it)."""
+    t0, t1 = WL.T_PAIR
+    wl = WL.real_workload("paper_1x300x11", 1, 300, 11, 0.2, WL.BASE_SEED + 50)
+    Xs, Ws = O.fixed_point(wl.X, WL.S_X), O.fixed_point(wl.W, WL.S_W)
+    bs = O.fixed_point(wl.b, WL.S_X + WL.S_W)
+    plain = O.plain_fixed_scores(Xs, Ws, bs)
+    assert max(abs(int(v)) for v in plain.flat) > t0 // 2
+    res = []
+    for k, pname in enumerate(("paper_t0", "paper_t1")):
+        p = WL.PARAMS[pname]
+        o = O.Oracle(p.n, list(p.q), p.P, p.t)
+        # encoding round trip and the constant closed form at this ring and t
+        z = rng(k).integers(0, p.t, p.n)
+        assert np.array_equal(o.decode(o.encode(z)), z.astype(np.uint64))
+        m = o.encode(np.full(p.n, 5))
+        assert m[0] == 5 and not m[1:].any()
+        keys = o.keygen(900 + k)
+        y = o.fast_matmul(keys, o.encrypt_rows(keys, Xs, seed=31), o.encode_weights(Ws), bs)
+        S, budget = o.scores_fast(keys, y, wl.rows, wl.classes)
+        assert budget > 20
+        assert np.array_equal(S, O.plain_scores(Xs, Ws, bs, p.t))
+        res.append(S)
+    assert np.array_equal(O.crt_pair(res[0], res[1], t0, t1), plain)

@@ -35,6 +35,16 @@ _Q4096 = (1073692673, 1073668097, 1073651713, 1073643521)
 # largest primes below 2^30 that are 1 mod 32768 (n = 16384)
 _Q16384 = (1073643521, 1073479681, 1073184769, 1073053697, 1072857089, 1072496641, 1071513601, 1071415297)
 
+# largest primes below 2^30 that are 1 mod 16384 (n = 8192): six data primes and P,
+# log2(Q P) = 210 <= 218, the 128-bit bound at n = 8192
+_Q8192 = (1073692673, 1073643521, 1073479681, 1073430529, 1073299457, 1073233921, 1073184769)
+
+# the paper's plaintext moduli (section "Private inference protocol"): a CRT pair,
+# t0 = 1073872897 (30 bits) and t1 = 114689 (16 bits), both 1 mod 2n at n = 8192,
+# and its fixed-point scales: inputs x 2^6, weights x 2^14, biases x 2^20
+T_PAIR = (1073872897, 114689)
+S_X, S_W = 6, 14
+
 PARAMS = {
     # tiny: n = 4096, t = 65537, two data primes + special prime
     "tiny": Params("tiny", 4096, _Q4096[:2], _Q4096[2], 65537),
@@ -42,6 +52,9 @@ PARAMS = {
     "tiny3": Params("tiny3", 4096, _Q4096[:3], _Q4096[3], 65537, insecure=True),
     # n = 16384, seven data primes + special prime, t = 786433 (20-bit, = 1 mod 32768)
     "n16k": Params("n16k", 16384, _Q16384[:7], _Q16384[7], 786433),
+    # the paper's parameter point: n = 8192, one context per plaintext modulus of the pair
+    "paper_t0": Params("paper_t0", 8192, _Q8192[:6], _Q8192[6], T_PAIR[0]),
+    "paper_t1": Params("paper_t1", 8192, _Q8192[:6], _Q8192[6], T_PAIR[1]),
 }
 
 
@@ -111,6 +124,28 @@ def uneven_requests(count: int = 64, seed: int = BASE_SEED + 4, max_rows: int = 
         out.append(Workload(f"req{r}", "n16k", int(rows[r]), int(fs[r]), 16, 0.01, seed + 1000 + r,
                             X, W[: int(fs[r])], b))
     return out
+
+
+def real_workload(name: str, rows: int, f: int, classes: int, p: float, seed: int) -> Workload:
+    """Real-valued inputs of the paper's precision point (section "Private
+    inference protocol"): features in [0, 2^8) (a Bernoulli(p) mask times
+    U[0, 256), mutation-count-like and sparse), weights and biases in (-1, 1),
+    float64.  The fixed-point scaling is the method's, not done here."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = (rng.random((rows, f)) < p) * rng.uniform(0.0, 256.0, size=(rows, f))
+    W = rng.uniform(-1.0, 1.0, size=(f, classes))
+    b = rng.uniform(-1.0, 1.0, size=classes)
+    return Workload(name, "paper_t0", rows, f, classes, p, seed, X, W, b)
+
+
+def paper_single(f: int = 40960, seed: int = BASE_SEED + 40) -> Workload:
+    """One patient x 40,960 features x 11 cancer types, real-valued."""
+    return real_workload(f"paper_1x{f}x11", 1, f, 11, 0.01, seed)
+
+
+def paper_batch(rows: int = 543, f: int = 40960, seed: int = BASE_SEED + 41) -> Workload:
+    """The paper's test set shape: 543 patients x 40,960 features x 11 cancer types."""
+    return real_workload(f"paper_{rows}x{f}x11", rows, f, 11, 0.01, seed)
 
 
 def poisson_arrivals(count: int, qps: float, seed: int = BASE_SEED + 5) -> np.ndarray:
