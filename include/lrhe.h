@@ -275,6 +275,25 @@ int lrhe_decrypt_scores(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* y, uin
 int lrhe_decrypt_scores_standard(lrhe_ctx* ctx, const lrhe_sk* sk, const uint32_t* y, uint32_t rows,
                                  uint32_t classes, uint32_t flags, int64_t* scores, double* min_budget_bits,
                                  void* stream);
+/* Client, the paper's precision point (section "Private inference protocol"):
+ * real inputs, weights and biases become integers by scaling with 2^s_x,
+ * 2^s_w and 2^(s_x + s_w) (s_x = 6, s_w = 14 there) and taking the nearest
+ * integer.  out[i] = nearest integer to in[i] 2^bits, ties to even (host
+ * double[count] -> host int64[count]).  EINVAL: null arguments, bits outside
+ * [0, 62], or a value that is not finite or whose scaled magnitude reaches
+ * 2^62. */
+int lrhe_fixed_point(const double* in, uint64_t count, int bits, int64_t* out);
+/* Client: recombination over the paper's CRT pair of plaintext moduli
+ * T = {t0, t1} (section "Private inference protocol": each plaintext is split
+ * into one polynomial mod t0 and one mod t1, each encrypted and computed on
+ * separately).  r0, r1: host int64[count] residues of the same scores mod t0
+ * and mod t1 (any representatives, e.g. the centred ones of
+ * lrhe_decrypt_scores); out: host int64[count], the unique integer in
+ * (-t0 t1 / 2, t0 t1 / 2] congruent to both.  Dividing it by 2^(s_x + s_w)
+ * gives the real-valued score.  EINVAL: null arguments, t0 or t1 below 2,
+ * t0 and t1 not coprime, or t0 t1 >= 2^63. */
+int lrhe_crt_combine(const int64_t* r0, const int64_t* r1, uint64_t count, uint64_t t0, uint64_t t1, int64_t* out);
+
 /* Debug decryption given the expected plaintext: decrypts `count` ciphertexts
  * (flags as above) and compares every slot with expected (host
  * int64[count][n], compared mod t).  Returns LRHE_ENOISE when any slot

@@ -402,3 +402,23 @@ class Server:
 def to_numpy_u32(t) -> np.ndarray:
     """Device int32 tensor of residues -> host uint32 array."""
     return t.cpu().numpy().view(np.uint32)
+
+
+def fixed_point(a, bits: int) -> np.ndarray:
+    """Real values to the paper's fixed-point integers, nearest integer to
+    a 2^bits (lrhe_fixed_point); same shape, int64."""
+    x = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.empty(x.shape, dtype=np.int64)
+    N.check(N.lib().lrhe_fixed_point(N.ptr(x), x.size, bits, N.ptr(out)))
+    return out
+
+
+def crt_combine(r0, r1, t0: int, t1: int) -> np.ndarray:
+    """Scores mod t0 and mod t1 to the integer in (-t0 t1 / 2, t0 t1 / 2]
+    congruent to both (lrhe_crt_combine); same shape, int64."""
+    a = np.ascontiguousarray(r0, dtype=np.int64)
+    b = np.ascontiguousarray(r1, dtype=np.int64)
+    assert a.shape == b.shape
+    out = np.empty(a.shape, dtype=np.int64)
+    N.check(N.lib().lrhe_crt_combine(N.ptr(a), N.ptr(b), a.size, t0, t1, N.ptr(out)))
+    return out

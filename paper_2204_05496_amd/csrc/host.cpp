@@ -983,6 +983,46 @@ extern "C" int lrhe_decrypt_check(lrhe_ctx* c, const lrhe_sk* sk, const uint32_t
   return LRHE_OK;
 }
 
+extern "C" int lrhe_fixed_point(const double* in, uint64_t count, int bits, int64_t* out) {
+  if ((!in || !out) && count) return fail(LRHE_EINVAL, "null argument");
+  if (bits < 0 || bits > 62) return fail(LRHE_EINVAL, "bits = %d outside [0, 62]", bits);
+  const double lim = std::ldexp(1.0, 62);
+  for (uint64_t i = 0; i < count; ++i) {
+    const double v = std::nearbyint(std::ldexp(in[i], bits));   // default rounding: nearest, ties to even
+    if (!std::isfinite(v) || std::fabs(v) >= lim)
+      return fail(LRHE_EINVAL, "value %llu (%g) does not fit after scaling by 2^%d", (unsigned long long)i, in[i], bits);
+    out[i] = (int64_t)v;
+  }
+  return LRHE_OK;
+}
+
+extern "C" int lrhe_crt_combine(const int64_t* r0, const int64_t* r1, uint64_t count, uint64_t t0, uint64_t t1,
+                                int64_t* out) {
+  if ((!r0 || !r1 || !out) && count) return fail(LRHE_EINVAL, "null argument");
+  if (t0 < 2 || t1 < 2) return fail(LRHE_EINVAL, "moduli must be at least 2");
+  const unsigned __int128 M = (unsigned __int128)t0 * t1;
+  if (M >> 63) return fail(LRHE_EINVAL, "t0 t1 must stay below 2^63");
+  // t0^-1 mod t1 by the extended Euclidean algorithm
+  int64_t a = (int64_t)(t0 % t1), b = (int64_t)t1, x0 = 1, x1 = 0;
+  while (b) {
+    const int64_t qd = a / b, r = a - qd * b, xr = x0 - qd * x1;
+    a = b; b = r; x0 = x1; x1 = xr;
+  }
+  if (a != 1) return fail(LRHE_EINVAL, "t0 and t1 are not coprime");
+  const uint64_t inv = (uint64_t)((x0 % (int64_t)t1 + (int64_t)t1) % (int64_t)t1);
+  const uint64_t m = (uint64_t)M, half = m / 2;
+  for (uint64_t i = 0; i < count; ++i) {
+    const uint64_t u = (uint64_t)(((r0[i] % (int64_t)t0) + (int64_t)t0) % (int64_t)t0);
+    const uint64_t v = (uint64_t)(((r1[i] % (int64_t)t1) + (int64_t)t1) % (int64_t)t1);
+    // z = u + t0 k with k = (v - u) t0^-1 mod t1, so z = u mod t0 and z = v mod t1
+    const uint64_t d = (v + t1 - u % t1) % t1;
+    const uint64_t k = (uint64_t)(((unsigned __int128)d * inv) % t1);
+    const uint64_t z = u + t0 * k;   // < t0 t1 < 2^63
+    out[i] = z > half ? (int64_t)z - (int64_t)m : (int64_t)z;
+  }
+  return LRHE_OK;
+}
+
 extern "C" int lrhe_host_transform(lrhe_ctx* c, uint32_t mod_index, uint32_t* a, int inverse) {
   if (!c || !a || mod_index > c->L + 1) return fail(LRHE_EINVAL, "bad argument");
   host_ntt_passes(c, (int)mod_index, a, inverse != 0);

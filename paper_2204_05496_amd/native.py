@@ -59,6 +59,8 @@ SIGNATURES = {
     "lrhe_model_create": (i32, [vp, vp, vp, u32, u32, vp, ctypes.POINTER(vp)]),
     "lrhe_model_destroy": (None, [vp]),
     "lrhe_matmul_fast": (i32, [vp, vp, vp, vp, u32, vp, vp, sz, vp]),
+    "lrhe_fixed_point": (i32, [vp, u64, i32, vp]),
+    "lrhe_crt_combine": (i32, [vp, vp, u64, u64, u64, vp]),
     "lrhe_matmul_fast_noalloc": (i32, [vp, vp, vp, vp, u32, vp, vp]),
     "lrhe_matmul_fast_pairs": (i32, [vp, vp, vp, vp, u32, u32, u32, i32, vp, vp, sz, vp]),
     "lrhe_matmul_standard": (i32, [vp, vp, vp, vp, vp, sz, vp]),

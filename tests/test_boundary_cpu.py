@@ -156,3 +156,44 @@ def test_fault_injection_switch(P):
     prev = lib.lrhe_fault_inject(2)
     assert lib.lrhe_fault_inject(-1) == 2
     assert lib.lrhe_fault_inject(prev) == 2
+
+
+def test_crt_combine_matches_oracle(P):
+    """lrhe_crt_combine against the oracle's recombination over the paper's pair,
+    on residues of integers spread over the whole signed range (centred and
+    non-negative representatives), and its refusals."""
+    t0, t1 = WL.T_PAIR
+    half = (t0 * t1) // 2
+    r = np.random.Generator(np.random.PCG64(5))
+    z = np.concatenate([r.integers(-half + 1, half + 1, size=2000, dtype=np.int64),
+                        np.array([0, 1, -1, half, -half + 1, 2 ** 44, -(2 ** 44)], dtype=np.int64)])
+    r0 = np.array([int(v) % t0 for v in z], dtype=np.int64)
+    r1 = np.array([int(v) % t1 for v in z], dtype=np.int64)
+    got = P.crt_combine(r0, r1, t0, t1)
+    assert np.array_equal(got, z)
+    assert list(got) == [int(v) for v in O.crt_pair(r0.astype(object), r1.astype(object), t0, t1)]
+    c0 = np.where(r0 > (t0 - 1) // 2, r0 - t0, r0)
+    c1 = np.where(r1 > (t1 - 1) // 2, r1 - t1, r1)
+    assert np.array_equal(P.crt_combine(c0, c1, t0, t1), z)
+    lib = P.native.lib()
+    one = np.zeros(1, dtype=np.int64)
+    p = P.native.ptr
+    assert lib.lrhe_crt_combine(p(one), p(one), 1, 6, 4, p(one)) == P.native.LRHE_EINVAL       # not coprime
+    assert lib.lrhe_crt_combine(p(one), p(one), 1, 2 ** 32 + 15, 2 ** 31 + 11, p(one)) == P.native.LRHE_EINVAL
+    assert lib.lrhe_crt_combine(p(one), p(one), 1, 1, 7, p(one)) == P.native.LRHE_EINVAL
+
+
+def test_fixed_point_matches_oracle(P):
+    """lrhe_fixed_point against the oracle's conversion on the paper-point
+    workload's inputs, weights and biases, ties, signs, and the refusals."""
+    wl = WL.paper_single(f=4096)
+    for a, bits in ((wl.X, WL.S_X), (wl.W, WL.S_W), (wl.b, WL.S_X + WL.S_W)):
+        assert np.array_equal(P.fixed_point(a, bits), O.fixed_point(a, bits))
+    ties = np.array([0.5, 1.5, 2.5, -0.5, -1.5, -2.5, 3.0, -7.25])
+    assert np.array_equal(P.fixed_point(ties, 0), O.fixed_point(ties, 0))
+    with pytest.raises(P.native.LrheError):
+        P.fixed_point(np.array([np.inf]), 6)
+    with pytest.raises(P.native.LrheError):
+        P.fixed_point(np.array([2.0 ** 60]), 6)
+    with pytest.raises(P.native.LrheError):
+        P.fixed_point(np.array([1.0]), 63)
