@@ -213,6 +213,94 @@ def bench_uneven(ctx, keys, P, WL, O, torch, args):
             "batched_pairs_per_s": round(sum(r.rows * r.classes for r, _, _, _ in reqs) / t_graph, 1)}
 
 
+def bench_paper_point(P, WL, O, torch, args):
+    """The paper's own parameter point (section "Private inference protocol"):
+    n = 8192, plaintext pair T = {t0, t1} (one context and key set per modulus),
+    fixed point with s_x = 6 and s_w = 14, on the paper's test-set shape (543
+    patients x 40,960 features x 11 cancer types).  Timed like the paper's
+    breakdown: encryption (both moduli), computation (Algorithm 1 for both),
+    decryption + CRT recombination + argmax; plus one prediction end to end."""
+    t0, t1 = WL.T_PAIR
+    wl = WL.paper_batch()
+    Xs, Ws = P.fixed_point(wl.X, WL.S_X), P.fixed_point(wl.W, WL.S_W)
+    bs = P.fixed_point(wl.b, WL.S_X + WL.S_W)
+    plain = O.plain_fixed_scores(Xs, Ws, bs).astype(np.int64)
+    Xd = torch.from_numpy(Xs).cuda()
+    sides = []
+    for k, pname in enumerate(("paper_t0", "paper_t1")):
+        ctx = P.Context.from_params(WL.PARAMS[pname], device=0)
+        keys = ctx.keygen(900 + k)
+        model = ctx.model(Ws, bs)
+        K = ctx.K(wl.f)
+        xct = ctx.empty_ct(wl.rows * K)
+        ws_enc = ctx.workspace(P.native.WS_ENCRYPT_ROWS, wl.rows, wl.f)
+        y = ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n))
+        ws = ctx.workspace(P.native.WS_MATMUL_FAST, wl.rows, wl.f, wl.classes)
+        ctx.encrypt_rows(keys, Xd, seed=32, out=xct, ws=ws_enc)
+        if not args.no_autotune:
+            ctx.autotune_fast(keys, model, xct, wl.rows, out=y, ws=ws)
+        sides.append((ctx, keys, model, xct, ws_enc, y, ws))
+
+    def run():
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for ctx, keys, model, xct, ws_enc, y, ws in sides:
+            ctx.encrypt_rows(keys, Xd, seed=32, out=xct, ws=ws_enc)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        for ctx, keys, model, xct, ws_enc, y, ws in sides:
+            ctx.matmul_fast(keys, model, xct, wl.rows, out=y, ws=ws)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        S = [ctx.scores_fast(keys, y, wl.rows, wl.classes)[0] for ctx, keys, model, xct, ws_enc, y, ws in sides]
+        Z = P.crt_combine(S[0], S[1], t0, t1)
+        cls = Z.argmax(1)
+        d = time.perf_counter()
+        return (b - a, c - b, d - c), Z, cls
+
+    run()
+    times = []
+    for _ in range(3):
+        tt, Z, cls = run()
+        times.append(tt)
+    assert np.array_equal(Z, plain) and np.array_equal(cls, plain.argmax(1))
+    enc, comp, dec = (float(np.median([t[i] for t in times])) for i in range(3))
+    total = enc + comp + dec
+    # one prediction, end to end (encrypt both, Algorithm 1 both, decrypt + CRT)
+    w1 = WL.paper_single()
+    X1 = torch.from_numpy(P.fixed_point(w1.X, WL.S_X)).cuda()
+    W1, b1 = P.fixed_point(w1.W, WL.S_W), P.fixed_point(w1.b, WL.S_X + WL.S_W)
+    one = []
+    for ctx, keys, *_ in sides:
+        m1 = ctx.model(W1, b1)
+        one.append((ctx, keys, m1, ctx.empty_ct(ctx.K(w1.f)), ctx.workspace(P.native.WS_ENCRYPT_ROWS, 1, w1.f),
+                    ctx.empty_ct(1), ctx.workspace(P.native.WS_MATMUL_FAST, 1, w1.f, w1.classes)))
+
+    def single():
+        for ctx, keys, m1, x1, we1, y1, ws1 in one:
+            ctx.encrypt_rows(keys, X1, seed=5, out=x1, ws=we1)
+            ctx.matmul_fast(keys, m1, x1, 1, out=y1, ws=ws1)
+        S1 = [ctx.scores_fast(keys, y1, 1, w1.classes)[0] for ctx, keys, m1, x1, we1, y1, ws1 in one]
+        return P.crt_combine(S1[0], S1[1], t0, t1)
+
+    Z1 = single()
+    assert np.array_equal(Z1, O.plain_fixed_scores(P.fixed_point(w1.X, WL.S_X), W1, b1).astype(np.int64))
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        single()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    return {"workload": wl.name, "bfv": {"n": 8192, "L": 6, "logQP": 210, "t": [t0, t1], "s_x": WL.S_X,
+                                          "s_w": WL.S_W},
+            "total_s": round(total, 4), "encrypt_s": round(enc, 4), "compute_s": round(comp, 4),
+            "decrypt_crt_s": round(dec, 4), "inferences_per_s": round(wl.rows / total, 1),
+            "single_prediction_ms": round(float(np.median(ts)) * 1e3, 3),
+            "paper_cpu_context": {"total_s": 46.77, "compute_s": 35.52, "encrypt_s": 10.40,
+                                  "single_prediction_s": 1.08, "hardware": "Threadripper 3960X, 24 threads, SEAL"}}
+
+
 def bench_serving(ctx, keys, P, WL, torch, args, ub):
     """Poisson arrivals of requests sized like the uneven workload at 0.5x and 0.8x
     the measured batch saturation rate; continuous batching in the native server."""
@@ -266,6 +354,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip latency / NTT / batching / serving measurements")
     ap.add_argument("--uneven", type=int, default=1, help="measure the uneven-requests batch (1/0)")
     ap.add_argument("--serve", type=int, default=1, help="measure the serving loop (1/0)")
+    ap.add_argument("--paper", type=int, default=1, help="measure the paper's parameter point (1/0)")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-budget", type=int, default=16, help="server partial-sum budget, GiB")
@@ -458,6 +547,10 @@ def main():
 
     if not args.no_extras:
         extras["valu_rates"] = valu_rates(lib)
+    if not args.no_extras and args.paper:
+        log("paper point")
+        extras["paper_point"] = bench_paper_point(P, WL, O, torch, args)
+        torch.cuda.empty_cache()
 
     if not args.no_extras and args.uneven:
         extras["uneven_batch"] = bench_uneven(ctx, keys, P, WL, O, torch, args)

@@ -333,8 +333,12 @@ def fixed_point(a, bits: int) -> np.ndarray:
 def plain_fixed_scores(Xs: np.ndarray, Ws: np.ndarray, bs) -> np.ndarray:
     """The exact integer result of the scaled computation, X_s W_s + b_s, with
     no reduction (it is what the CRT pair must give back); Python integers."""
-    S = np.asarray(Xs, dtype=object) @ np.asarray(Ws, dtype=object) + np.asarray(bs, dtype=object)[None, :]
-    return S
+    X64, W64, b64 = (np.asarray(a, dtype=np.int64) for a in (Xs, Ws, bs))
+    bound = int(np.abs(X64).max(initial=0)) * int(np.abs(W64).max(initial=0)) * X64.shape[1] + \
+        int(np.abs(b64).max(initial=0))
+    if bound < 2**62:   # every partial sum fits: int64 arithmetic is exact
+        return (X64 @ W64 + b64[None, :]).astype(object)
+    return X64.astype(object) @ W64.astype(object) + b64.astype(object)[None, :]
 
 
 def crt_pair(r0, r1, t0: int, t1: int) -> np.ndarray:
