@@ -173,11 +173,14 @@ def bench_uneven(ctx, keys, P, WL, O, torch, args):
     with torch.cuda.stream(side):
         b.capture(side)
     side.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.run()
-    torch.cuda.synchronize()
-    t_graph = time.perf_counter() - t0
+    reps = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+    t_graph = float(np.median(reps))
     # correctness of the replay on a few requests (scores = X W + b mod t)
     for r, xct, m, y in reqs[:3]:
         S, _ = ctx.scores_fast(keys, y, r.rows, r.classes)
@@ -206,11 +209,47 @@ def bench_uneven(ctx, keys, P, WL, O, torch, args):
     torch.cuda.empty_cache()
     return {"workload": f"uneven_{len(reqs)}req", "requests": len(reqs), "individuals": rows_total,
             "pairs": sum(r.rows * r.classes for r, _, _, _ in reqs), "tuning": tuned,
-            "graph_s": round(t_graph, 3), "inferences_per_s": round(rows_total / t_graph, 2),
+            "graph_s": round(t_graph, 3), "graph_replays": 3, "inferences_per_s": round(rows_total / t_graph, 2),
             "requests_per_s": round(len(reqs) / t_graph, 3),
             "per_request_alone_s": round(t_alone, 3), "alone_inferences_per_s": round(rows_total / t_alone, 2),
             "one_ciphertext_at_a_time_pairs_per_s": round(1.0 / t_one, 2),
             "batched_pairs_per_s": round(sum(r.rows * r.classes for r, _, _, _ in reqs) / t_graph, 1)}
+
+
+def bench_binary(ctx, keys, P, WL, O, torch, args):
+    """The one-vs-rest binary models (section "Binary models"): 11 models with
+    their own features (f ~ U{10,000..40,000}) and one output each, on the 543
+    patients of the paper's test set, as one planned batch (median of 3 runs)
+    against the same models run one after another."""
+    models = WL.binary_models()
+    reqs = []
+    for k, wl in enumerate(models):
+        xct = ctx.encrypt_rows(keys, torch.from_numpy(wl.X).cuda(), seed=500 + k)
+        reqs.append((xct, wl.rows, ctx.model(wl.W, wl.b), ctx.empty_ct(-(-wl.rows // ctx.n))))
+    b = P.Batch(ctx, keys, reqs)
+    b.run()
+    torch.cuda.synchronize()
+    for wl, (xct, rows, m, y) in zip(models, reqs):
+        S, _ = ctx.scores_fast(keys, y, rows, 1)
+        assert np.array_equal(S, O.plain_scores(wl.X, wl.W, wl.b, ctx.t))
+    tb, ta = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for xct, rows, m, y in reqs:
+            ctx.matmul_fast(keys, m, xct, rows, out=y)
+        torch.cuda.synchronize()
+        ta.append(time.perf_counter() - t0)
+    b.close()
+    rows = models[0].rows
+    tbm, tam = float(np.median(tb)), float(np.median(ta))
+    return {"workload": f"binary_{len(models)}x{rows}", "models": len(models), "individuals": rows,
+            "features": [wl.f for wl in models], "batch_s": round(tbm, 4), "alone_s": round(tam, 4),
+            "model_evaluations_per_s": round(len(models) * rows / tbm, 1)}
 
 
 def bench_paper_point(P, WL, O, torch, args):
@@ -301,9 +340,11 @@ def bench_paper_point(P, WL, O, torch, args):
                                   "single_prediction_s": 1.08, "hardware": "Threadripper 3960X, 24 threads, SEAL"}}
 
 
-def bench_serving(ctx, keys, P, WL, torch, args, ub):
+def bench_serving(ctx, keys, P, WL, O, torch, args, ub):
     """Poisson arrivals of requests sized like the uneven workload at 0.5x and 0.8x
-    the measured batch saturation rate; continuous batching in the native server."""
+    the measured batch saturation rate; continuous batching in the native server.
+    Every served result is decrypted and checked against X W + b mod t after the
+    timed run."""
     reqs = _uneven_inputs(ctx, keys, P, WL, torch, args.serve_requests)
     sat = ub["requests_per_s"]
     res = {}
@@ -328,6 +369,10 @@ def bench_serving(ctx, keys, P, WL, torch, args, ub):
         lat = np.array([srv.poll(i)[1] for i in ids])
         st = srv.stats()
         srv.close()
+        for r, xct, m, y in reqs:
+            S, _ = ctx.scores_fast(keys, y, r.rows, r.classes)
+            assert np.array_equal(S, O.plain_scores(r.X, r.W, r.b, ctx.t)), f"served {r.name}"
+            y.zero_()
         rows_total = sum(r.rows for r, _, _, _ in reqs)
         res[f"qps_{frac}x"] = {"offered_req_per_s": round(qps, 3), "requests": len(reqs),
                                "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
@@ -355,8 +400,9 @@ def main():
     ap.add_argument("--uneven", type=int, default=1, help="measure the uneven-requests batch (1/0)")
     ap.add_argument("--serve", type=int, default=1, help="measure the serving loop (1/0)")
     ap.add_argument("--paper", type=int, default=1, help="measure the paper's parameter point (1/0)")
+    ap.add_argument("--binary", type=int, default=1, help="measure the one-vs-rest binary models (1/0)")
     ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-budget", type=int, default=16, help="server partial-sum budget, GiB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -552,10 +598,15 @@ def main():
         extras["paper_point"] = bench_paper_point(P, WL, O, torch, args)
         torch.cuda.empty_cache()
 
+    if not args.no_extras and args.binary:
+        log("binary models")
+        extras["binary_models"] = bench_binary(ctx, keys, P, WL, O, torch, args)
+        torch.cuda.empty_cache()
+
     if not args.no_extras and args.uneven:
         extras["uneven_batch"] = bench_uneven(ctx, keys, P, WL, O, torch, args)
     if not args.no_extras and args.serve and "uneven_batch" in extras:
-        extras["serving"] = bench_serving(ctx, keys, P, WL, torch, args, extras["uneven_batch"])
+        extras["serving"] = bench_serving(ctx, keys, P, WL, O, torch, args, extras["uneven_batch"])
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,

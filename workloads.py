@@ -126,6 +126,22 @@ def uneven_requests(count: int = 64, seed: int = BASE_SEED + 4, max_rows: int = 
     return out
 
 
+def binary_models(rows: int = 543, count: int = 11, seed: int = BASE_SEED + 60, params: str = "n16k",
+                  f_lo: int = 10000, f_hi: int = 40000, p: float = 0.01):
+    """One-vs-rest binary models (section "Binary models"): one model per cancer
+    type, each with its own selected features (f_m ~ U{f_lo..f_hi}) and a single
+    output (|Y| = 1), evaluated on the same individuals; model m's inputs are the
+    individuals' values of its own features."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fs = rng.integers(f_lo, f_hi + 1, size=count)
+    out = []
+    for m in range(count):
+        f = int(fs[m])
+        out.append(Workload(f"binary{m}", params, rows, f, 1, p, seed + 100 + m, features(rows, f, p, seed + 100 + m),
+                            weights(f, 1, seed + 200 + m), biases(1, seed + 300 + m)))
+    return out
+
+
 def real_workload(name: str, rows: int, f: int, classes: int, p: float, seed: int) -> Workload:
     """Real-valued inputs of the paper's precision point (section "Private
     inference protocol"): features in [0, 2^8) (a Bernoulli(p) mask times
