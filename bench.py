@@ -340,6 +340,131 @@ def bench_paper_point(P, WL, O, torch, args):
                                   "single_prediction_s": 1.08, "hardware": "Threadripper 3960X, 24 threads, SEAL"}}
 
 
+class PaperPair:
+    """The paper's parameter point as two contexts (t0 and t1, own keys each):
+    timed encryption / computation / decryption + CRT for the fast method and for
+    the standard baseline on real-valued inputs in fixed point."""
+
+    def __init__(self, P, WL, O, torch):
+        self.P, self.WL, self.O, self.torch = P, WL, O, torch
+        self.ctx, self.keys = [], []
+        for k, pname in enumerate(("paper_t0", "paper_t1")):
+            ctx = P.Context.from_params(WL.PARAMS[pname], device=0)
+            self.ctx.append(ctx)
+            self.keys.append(ctx.keygen(900 + k))
+
+    def scaled(self, wl):
+        P, WL = self.P, self.WL
+        return (P.fixed_point(wl.X, WL.S_X), P.fixed_point(wl.W, WL.S_W), P.fixed_point(wl.b, WL.S_X + WL.S_W))
+
+    def _time(self, fn):
+        self.torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = fn()
+        self.torch.cuda.synchronize()
+        return time.perf_counter() - a, r
+
+    def fast(self, wl, reps=3, autotune=False):
+        """(encrypt_s, compute_s, decrypt_crt_s) medians and the recombined scores."""
+        P, torch = self.P, self.torch
+        Xs, Ws, bs = self.scaled(wl)
+        Xd = torch.from_numpy(Xs).cuda()
+        sides = []
+        for ctx, keys in zip(self.ctx, self.keys):
+            model = ctx.model(Ws, bs)
+            xct = ctx.empty_ct(wl.rows * ctx.K(wl.f))
+            we = ctx.workspace(P.native.WS_ENCRYPT_ROWS, wl.rows, wl.f)
+            y = ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n))
+            ws = ctx.workspace(P.native.WS_MATMUL_FAST, wl.rows, wl.f, wl.classes)
+            if autotune:
+                ctx.encrypt_rows(keys, Xd, seed=32, out=xct, ws=we)
+                ctx.autotune_fast(keys, model, xct, wl.rows, out=y, ws=ws)
+            sides.append((ctx, keys, model, xct, we, y, ws))
+        T = []
+        for _ in range(reps + 1):
+            te, _ = self._time(lambda: [c.encrypt_rows(k, Xd, seed=32, out=x, ws=we) for c, k, m, x, we, y, ws in sides])
+            tc, _ = self._time(lambda: [c.matmul_fast(k, m, x, wl.rows, out=y, ws=ws) for c, k, m, x, we, y, ws in sides])
+            td, Z = self._time(lambda: P.crt_combine(*[c.scores_fast(k, y, wl.rows, wl.classes)[0]
+                                                       for c, k, m, x, we, y, ws in sides], *self.WL.T_PAIR))
+            T.append((te, tc, td))
+        del sides, Xd
+        torch.cuda.empty_cache()
+        return tuple(float(np.median([t[i] for t in T[1:]])) for i in range(3)), Z
+
+    def standard(self, wl, reps=2):
+        """The standard baseline (individuals in slots, one ciphertext per feature)."""
+        P, torch = self.P, self.torch
+        Xs, Ws, bs = self.scaled(wl)
+        Xd = torch.from_numpy(Xs).cuda()
+        T = []
+        for _ in range(reps):
+            te = tc = td = 0.0
+            S = []
+            for ctx, keys in zip(self.ctx, self.keys):
+                model = ctx.model(Ws, bs)
+                we = ctx.workspace(P.native.WS_ENCRYPT_COLS, wl.rows, wl.f)
+                t, fct = self._time(lambda: ctx.encrypt_cols(keys, Xd, seed=33, ws=we))
+                te += t
+                del we
+                t, ys = self._time(lambda: ctx.matmul_standard(model, fct))
+                tc += t
+                del fct
+                t, s_ = self._time(lambda: ctx.scores_standard(keys, ys, wl.rows)[0])
+                td += t
+                S.append(s_)
+                torch.cuda.empty_cache()
+            t, Z = self._time(lambda: P.crt_combine(S[0], S[1], *self.WL.T_PAIR))
+            T.append((te, tc, td + t))
+        return tuple(float(np.median([x[i] for x in T])) for i in range(3)), Z
+
+    def check(self, wl, Z, rows=64):
+        """Recombined scores against X_s W_s + b_s (the first `rows` individuals)."""
+        Xs, Ws, bs = self.scaled(wl)
+        r = min(rows, wl.rows)
+        assert np.array_equal(Z[:r], self.O.plain_fixed_scores(Xs[:r], Ws, bs).astype(np.int64))
+
+
+def run_sweeps(P, WL, O, torch, path):
+    """Curves shaped like the paper's timing figures, at its parameter point:
+    time against the number of features (543 patients), against the number of
+    test samples (40,960 features), and fast against standard for 1 to 8,192
+    individuals (40,960 features); each point's scores are checked."""
+    pp = PaperPair(P, WL, O, torch)
+    out = {"params": {"n": 8192, "L": 6, "t": list(WL.T_PAIR), "s_x": WL.S_X, "s_w": WL.S_W, "classes": 11}}
+    # launch choices tuned once per tile class (a 543-patient job and a single patient)
+    pp.fast(WL.paper_batch(), reps=1, autotune=True)
+    pp.fast(WL.paper_single(), reps=1, autotune=True)
+    row = lambda t, n: {"encrypt_s": round(t[0], 5), "compute_s": round(t[1], 5), "decrypt_s": round(t[2], 5),
+                        "total_s": round(sum(t), 5), "n": n}
+    out["features"] = []
+    for f in (16384, 20480, 24576, 28672, 32768, 36864, 40960):
+        wl = WL.paper_batch(f=f)
+        t, Z = pp.fast(wl)
+        pp.check(wl, Z)
+        out["features"].append(row(t, f))
+        log("sweep features", f, out["features"][-1])
+    out["samples"] = []
+    for rows in (1, 2, 4, 8, 16, 32, 64, 128, 256, 543):
+        wl = WL.paper_batch(rows=rows)
+        t, Z = pp.fast(wl)
+        pp.check(wl, Z)
+        out["samples"].append(row(t, rows))
+        log("sweep samples", rows, out["samples"][-1])
+    out["fast_vs_standard"] = []
+    for rows in (1, 8, 64, 512, 4096, 8192):
+        wl = WL.paper_batch(rows=rows)
+        tf, Zf = pp.fast(wl, reps=2)
+        pp.check(wl, Zf)
+        ts, Zs = pp.standard(wl)
+        assert np.array_equal(Zs, Zf)
+        out["fast_vs_standard"].append({"individuals": rows, "fast": row(tf, rows), "standard": row(ts, rows)})
+        log("sweep fast vs standard", rows, out["fast_vs_standard"][-1])
+        del wl
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(ctx, keys, P, WL, O, torch, args, ub):
     """Poisson arrivals of requests sized like the uneven workload at 0.5x and 0.8x
     the measured batch saturation rate; continuous batching in the native server.
@@ -404,6 +529,9 @@ def main():
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-budget", type=int, default=16, help="server partial-sum budget, GiB")
+    ap.add_argument("--sweeps", default="", metavar="PATH",
+                    help="instead of the benchmark, run the timing sweeps at the paper's parameter point "
+                         "and write them to PATH as JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -417,6 +545,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs an MI355X"
     lib = P.native.lib()
+    if args.sweeps:
+        run_sweeps(P, WL, O, torch, args.sweeps)
+        return
     p = WL.PARAMS["n16k"]
     wl = WL.batch(rows=args.rows, f=args.features)
     ctx = P.Context.from_params(p, device=0)
