@@ -382,6 +382,42 @@ int lrhe_prof_valu_rate(int op, int iters, int reps, double* per_s, double* best
  * gives the initial k.  Returns the previous k; k < 0 only reads it. */
 int64_t lrhe_fault_inject(int64_t k);
 
+/* Wire format of the private inference protocol (section "Private inference
+ * protocol": the client sends the encrypted inputs, and once its evaluation
+ * keys, to the server, which returns the encrypted results; keys are kept
+ * across restarts).  A message is a 64-byte header (magic "LRHEWIR1",
+ * version 1, kind, n, L, t, a digest of the moduli, count, payload size and
+ * an FNV-1a 64 checksum of the payload) and a payload of canonical
+ * coefficient-form residues, little-endian u32: kind LRHE_WIRE_CT
+ * ciphertexts [count][2][L][n]; LRHE_WIRE_GK Galois keys
+ * [ngal][L digits][2][L+1 moduli][n]; LRHE_WIRE_PK public key [2][L][n];
+ * LRHE_WIRE_SK secret key int8 [n].  The caller owns every buffer. */
+enum { LRHE_WIRE_CT = 1, LRHE_WIRE_GK = 2, LRHE_WIRE_PK = 3, LRHE_WIRE_SK = 4 };
+/* Message size in bytes for `count` ciphertexts (kind LRHE_WIRE_CT) or one key. */
+int lrhe_wire_bytes(lrhe_ctx* ctx, int kind, uint64_t count, uint64_t* bytes);
+/* ct: `count` ciphertexts in the library's layout (device memory, or host
+ * memory with LRHE_CT_HOST; the copy runs on `stream`, which is synchronized);
+ * out: host buffer of cap >= lrhe_wire_bytes bytes.  EINVAL: null, short
+ * buffer, unknown flags; EDEVICE: copy error or device memory on a host-only
+ * context. */
+int lrhe_ct_serialize(lrhe_ctx* ctx, const uint32_t* ct, uint32_t count, uint32_t flags, uint8_t* out, uint64_t cap,
+                      void* stream);
+/* Reads a ciphertext message into ct_out (room for max_count ciphertexts,
+ * device memory or host memory with LRHE_CT_HOST); count (optional) receives
+ * the number read.  EINVAL when the message is malformed, of another kind,
+ * made under other parameters, fails its checksum, holds non-canonical
+ * residues or more than max_count ciphertexts; nothing is written then. */
+int lrhe_ct_deserialize(lrhe_ctx* ctx, const uint8_t* in, uint64_t bytes, uint32_t flags, uint32_t* ct_out,
+                        uint32_t max_count, uint32_t* count, void* stream);
+/* kind LRHE_WIRE_GK (key: const lrhe_gk*), LRHE_WIRE_PK (const lrhe_pk*) or
+ * LRHE_WIRE_SK (const lrhe_sk*; the secret key stays with the client). */
+int lrhe_key_serialize(lrhe_ctx* ctx, int kind, const void* key, uint8_t* out, uint64_t cap);
+/* New key objects from messages, checked as in lrhe_ct_deserialize (the secret
+ * key's coefficients must be ternary); owned by the caller (*_destroy). */
+int lrhe_gk_deserialize(lrhe_ctx* ctx, const uint8_t* in, uint64_t bytes, lrhe_gk** out);
+int lrhe_pk_deserialize(lrhe_ctx* ctx, const uint8_t* in, uint64_t bytes, lrhe_pk** out);
+int lrhe_sk_deserialize(lrhe_ctx* ctx, const uint8_t* in, uint64_t bytes, lrhe_sk** out);
+
 /* Keys in canonical coefficient form on the host: pk as uint32 [2][L][n];
  * gk as uint32 [ngal][L digits][2][L+1 moduli][n] (last modulus = P). */
 int lrhe_pk_export(lrhe_ctx* ctx, const lrhe_pk* pk, uint32_t* host_out);

@@ -150,6 +150,57 @@ class Context:
         N.check(N.lib().lrhe_sk_export(self.h, keys.sk, N.ptr(out)))
         return out
 
+    # ---------------------------------------------------------------- wire format
+    def _wire_bytes(self, kind: int, count: int = 1) -> int:
+        b = ctypes.c_uint64()
+        N.check(N.lib().lrhe_wire_bytes(self.h, kind, count, ctypes.byref(b)))
+        return b.value
+
+    def serialize_ct(self, ct) -> bytes:
+        """Ciphertexts (device tensor, or host uint32 array) as one wire message."""
+        host = isinstance(ct, np.ndarray)
+        if host:
+            ct = np.ascontiguousarray(ct, dtype=np.uint32)
+        else:
+            ct = ct.contiguous()
+        count = ct.shape[0]
+        out = np.empty(self._wire_bytes(N.WIRE_CT, count), dtype=np.uint8)
+        N.check(N.lib().lrhe_ct_serialize(self.h, N.ptr(ct), count, N.CT_HOST if host else 0, N.ptr(out), out.size,
+                                          None if host else _stream()))
+        return out.tobytes()
+
+    def deserialize_ct(self, msg: bytes, out=None, host: bool = False):
+        """A ciphertext message into a device tensor (or into `out`; host=True: a
+        host uint32 array)."""
+        buf = np.frombuffer(msg, dtype=np.uint8)
+        count = int.from_bytes(msg[40:48], "little") if len(msg) >= 64 else 0
+        if out is None:
+            out = np.zeros((count, 2, self.L, self.n), dtype=np.uint32) if host else self.empty_ct(count)
+        got = ctypes.c_uint32()
+        N.check(N.lib().lrhe_ct_deserialize(self.h, N.ptr(buf), buf.size, N.CT_HOST if host else 0, N.ptr(out),
+                                            out.shape[0], ctypes.byref(got), None if host else _stream()))
+        return out[:got.value]
+
+    def serialize_key(self, keys: Keys, kind: int) -> bytes:
+        """One key of `keys` (N.WIRE_GK, N.WIRE_PK or N.WIRE_SK) as a wire message."""
+        key = {N.WIRE_GK: keys.gk, N.WIRE_PK: keys.pk, N.WIRE_SK: keys.sk}[kind]
+        out = np.empty(self._wire_bytes(kind), dtype=np.uint8)
+        N.check(N.lib().lrhe_key_serialize(self.h, kind, key, N.ptr(out), out.size))
+        return out.tobytes()
+
+    def load_keys(self, sk: bytes = None, pk: bytes = None, gk: bytes = None) -> Keys:
+        """Keys from wire messages (any subset): the client keeps sk and pk, the
+        server receives gk."""
+        handles = []
+        for msg, fn in ((sk, N.lib().lrhe_sk_deserialize), (pk, N.lib().lrhe_pk_deserialize),
+                        (gk, N.lib().lrhe_gk_deserialize)):
+            h = ctypes.c_void_p()
+            if msg is not None:
+                buf = np.frombuffer(msg, dtype=np.uint8)
+                N.check(fn(self.h, N.ptr(buf), buf.size, ctypes.byref(h)))
+            handles.append(h if msg is not None else None)
+        return Keys(self, *handles)
+
     # ---------------------------------------------------------------- client
     def _as_dev_i64(self, X):
         torch = _torch()

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 
 # (source, object, extra flags): the key-switch launchers build once per ring dimension
 SOURCES = [("kernels.hip", "kernels.hip.o", []), ("host.cpp", "host.cpp.o", []), ("prof.cpp", "prof.cpp.o", []),
-           ("plan.cpp", "plan.cpp.o", []), ("valu_rate.hip", "valu_rate.hip.o", [])] + \
+           ("plan.cpp", "plan.cpp.o", []), ("valu_rate.hip", "valu_rate.hip.o", []), ("wire.cpp", "wire.cpp.o", [])] + \
           [("ks_step.hip", f"ks_step.ln{ln}.o", [f"-DLRHE_KS_LOGN={ln}"]) for ln in range(10, 16)]
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

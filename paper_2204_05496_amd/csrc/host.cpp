@@ -529,27 +529,71 @@ static void automorph_int(const std::vector<int32_t>& a, uint32_t g, uint32_t n,
   }
 }
 
-extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk** sk_out, lrhe_pk** pk_out,
-                           lrhe_gk** gk_out) {
-  if (!c) return fail(LRHE_EINVAL, "null context");
+namespace lrhe {
+void host_transform_limb(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse) { host_ntt(c, mi, a, inverse); }
+
+// s in evaluation form for every modulus (data primes and P), [L+1][n]
+static std::vector<uint32_t> secret_eval(const lrhe_ctx* c, const int32_t* s) {
   const uint32_t n = c->n, L = c->L;
-  std::vector<int32_t> s, e;
-  sample_ternary(seed, KIND_SECRET, 0, n, s);
-  // s in evaluation form for every modulus (data primes and P)
   std::vector<uint32_t> S((size_t)(L + 1) * n);
   for (uint32_t r = 0; r <= L; ++r) {
     uint32_t* Sr = &S[(size_t)r * n];
     for (uint32_t k = 0; k < n; ++k) Sr[k] = smod(s[k], c->q[r]);
     host_ntt(c, (int)r, Sr, false);
   }
+  return S;
+}
+
+lrhe_sk* make_sk(const lrhe_ctx* c, const int32_t* s) {
+  const uint32_t n = c->n, L = c->L;
+  const std::vector<uint32_t> S = secret_eval(c, s);
   auto* sk = new lrhe_sk();
   sk->n = n;
   sk->L = L;
-  sk->s.assign(s.begin(), s.end());
+  sk->s.assign(s, s + n);
   sk->S.assign(S.begin(), S.begin() + (size_t)L * n);
   sk->Sm.resize((size_t)L * n);
   for (uint32_t j = 0; j < L; ++j)
     for (uint32_t k = 0; k < n; ++k) sk->Sm[(size_t)j * n + k] = to_mont(sk->S[(size_t)j * n + k], c->mods[j]);
+  return sk;
+}
+
+// device copy of a public key from its host evaluation form (Montgomery words)
+hipError_t upload_pk(const lrhe_ctx* c, lrhe_pk* pk) {
+  if (c->device < 0) return hipSuccess;
+  const uint32_t n = c->n, L = c->L;
+  hipError_t err = hipSetDevice(c->device);
+  if (err == hipSuccess) err = dev_malloc((void**)&pk->d, pk->h.size() * 4);
+  if (err != hipSuccess) return err;
+  std::vector<uint32_t> mont(pk->h.size());
+  for (size_t x = 0; x < mont.size(); ++x) mont[x] = to_mont(pk->h[x], c->mods[(x / n) % L]);
+  return hipMemcpy(pk->d, mont.data(), mont.size() * 4, hipMemcpyHostToDevice);
+}
+
+// device copy of the Galois keys from their host evaluation form (layout [g][r][i][x][n])
+hipError_t upload_gk(const lrhe_ctx* c, lrhe_gk* gk) {
+  if (c->device < 0) return hipSuccess;
+  const uint32_t n = c->n, L = c->L;
+  std::vector<uint32_t> mont(gk->words);
+  for (size_t x = 0; x < mont.size(); ++x) {
+    const uint32_t r = (uint32_t)((x / ((size_t)L * 2 * n)) % (L + 1));
+    mont[x] = to_mont(gk->h[x], c->mods[r]);
+  }
+  hipError_t err = hipSetDevice(c->device);
+  if (err == hipSuccess) err = dev_malloc((void**)&gk->d, gk->words * 4);
+  if (err == hipSuccess) err = hipMemcpy(gk->d, mont.data(), gk->words * 4, hipMemcpyHostToDevice);
+  return err;
+}
+}  // namespace lrhe
+
+extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk** sk_out, lrhe_pk** pk_out,
+                           lrhe_gk** gk_out) {
+  if (!c) return fail(LRHE_EINVAL, "null context");
+  const uint32_t n = c->n, L = c->L;
+  std::vector<int32_t> s, e;
+  sample_ternary(seed, KIND_SECRET, 0, n, s);
+  const std::vector<uint32_t> S = secret_eval(c, s.data());
+  lrhe_sk* sk = make_sk(c, s.data());
   // public key: pk = (-(a s + e), a) mod Q, evaluation form
   auto* pk = new lrhe_pk();
   pk->h.assign((size_t)2 * L * n, 0);
@@ -568,18 +612,11 @@ extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk*
       pk->h[(size_t)(L + j) * n + k] = A[k];
     }
   }
-  const bool dev = c->device >= 0;
-  hipError_t err = dev ? hipSetDevice(c->device) : hipSuccess;
-  if (err == hipSuccess && dev) err = dev_malloc((void**)&pk->d, pk->h.size() * 4);
+  hipError_t err = upload_pk(c, pk);
   if (err != hipSuccess) {
     delete sk;
-    delete pk;
-    return fail(LRHE_EDEVICE, "pk allocation: %s", hipGetErrorString(err));
-  }
-  {
-    std::vector<uint32_t> mont(pk->h.size());
-    for (size_t x = 0; x < mont.size(); ++x) mont[x] = to_mont(pk->h[x], c->mods[(x / n) % L]);
-    if (dev) err = hipMemcpy(pk->d, mont.data(), mont.size() * 4, hipMemcpyHostToDevice);
+    lrhe_pk_destroy(pk);
+    return fail(LRHE_EDEVICE, "pk upload: %s", hipGetErrorString(err));
   }
   lrhe_gk* gk = nullptr;
   if (err == hipSuccess && with_galois) {
@@ -617,15 +654,7 @@ extern "C" int lrhe_keygen(lrhe_ctx* c, uint64_t seed, int with_galois, lrhe_sk*
           }
         }
       }
-    std::vector<uint32_t> mont(gk->words);
-    for (size_t x = 0; x < mont.size(); ++x) {
-      const uint32_t r = (uint32_t)((x / ((size_t)L * 2 * n)) % (L + 1));
-      mont[x] = to_mont(gk->h[x], c->mods[r]);
-    }
-    if (dev) {
-      err = dev_malloc((void**)&gk->d, gk->words * 4);
-      if (err == hipSuccess) err = hipMemcpy(gk->d, mont.data(), gk->words * 4, hipMemcpyHostToDevice);
-    }
+    err = upload_gk(c, gk);
   }
   if (err != hipSuccess) {
     delete sk;

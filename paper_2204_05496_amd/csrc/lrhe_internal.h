@@ -213,6 +213,16 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
                        uint32_t* ACC, uint64_t acc_slots, uint32_t* part, hipStream_t s);
 hipError_t launch_standard(const lrhe_ctx* c, const lrhe_model* m, const uint32_t* fct, uint32_t* y_out,
                            hipStream_t s);
+// host-side key and transform helpers shared by keygen and the wire format
+// (host.cpp): a limb's host transform (inverse: evaluation -> coefficients),
+// a secret key from its ternary coefficients, and the device copies of keys
+// whose host evaluation form is filled in
+void host_transform_limb(const lrhe_ctx* c, int mi, uint32_t* a, bool inverse);
+lrhe_sk* make_sk(const lrhe_ctx* c, const int32_t* s);
+hipError_t upload_pk(const lrhe_ctx* c, lrhe_pk* pk);
+hipError_t upload_gk(const lrhe_ctx* c, lrhe_gk* gk);
+int fail(int code, const char* fmt, ...);
+
 // device address of the fixed scratch array on a device: resolved once per
 // device (with that device current) by scratch_resolve, nullptr before
 hipError_t scratch_resolve(int device);

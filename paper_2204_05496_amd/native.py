@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "liblrhe.so")
 
 LRHE_OK, LRHE_EINVAL, LRHE_EPARAM, LRHE_ENOMEM, LRHE_EAGAIN, LRHE_EDEVICE, LRHE_ENOISE = 0, -1, -2, -3, -4, -5, -6
+WIRE_CT, WIRE_GK, WIRE_PK, WIRE_SK = 1, 2, 3, 4
 WS_ENCRYPT_ROWS, WS_ENCRYPT_COLS, WS_MATMUL_FAST, WS_MATMUL_STANDARD = 1, 2, 3, 4
 CT_HOST = 1   # decryption flag: the ciphertexts are in host memory
 # variants of the key-switch inner-product kernel behind the "mac_mode" tuning key;
@@ -70,6 +71,13 @@ SIGNATURES = {
     "lrhe_decrypt_scores_standard": (i32, [vp, vp, vp, u32, u32, u32, vp, ctypes.POINTER(ctypes.c_double), vp]),
     "lrhe_decrypt_check": (i32, [vp, vp, vp, u32, vp, u32, vp, ctypes.POINTER(u64), vp]),
     "lrhe_fault_inject": (i64, [i64]),
+    "lrhe_wire_bytes": (i32, [vp, i32, u64, ctypes.POINTER(u64)]),
+    "lrhe_ct_serialize": (i32, [vp, vp, u32, u32, vp, u64, vp]),
+    "lrhe_ct_deserialize": (i32, [vp, vp, u64, u32, vp, u32, ctypes.POINTER(u32), vp]),
+    "lrhe_key_serialize": (i32, [vp, i32, vp, vp, u64]),
+    "lrhe_gk_deserialize": (i32, [vp, vp, u64, ctypes.POINTER(vp)]),
+    "lrhe_pk_deserialize": (i32, [vp, vp, u64, ctypes.POINTER(vp)]),
+    "lrhe_sk_deserialize": (i32, [vp, vp, u64, ctypes.POINTER(vp)]),
     "lrhe_host_transform": (i32, [vp, u32, vp, i32]),
     "lrhe_to_coeff": (i32, [vp, vp, u64, vp, vp]),
     "lrhe_pk_export": (i32, [vp, vp, vp]),
