@@ -25,6 +25,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bfv_oracle.c")
 _LIB = os.path.join(_HERE, "libbfv_oracle.so")
+# a prebuilt oracle library in its place (the sanitizer build of the CPU tests)
+_LIB_OVERRIDE = os.environ.get("LRHE_ORACLE_LIB")
 
 u64p = ctypes.POINTER(ctypes.c_uint64)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -46,7 +48,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        L = ctypes.CDLL(build())
+        L = ctypes.CDLL(_LIB_OVERRIDE or build())
         vp = ctypes.c_void_p
         L.ora_ctx_new.restype = vp
         L.ora_ctx_new.argtypes = [ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64]

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "liblrhe.so")
+# LRHE_LIB names another build of the same library (the sanitizer build of the
+# CPU tests); there is no other implementation to fall back to
+LIBPATH = os.environ.get("LRHE_LIB") or os.path.join(HERE, "liblrhe.so")
 
 LRHE_OK, LRHE_EINVAL, LRHE_EPARAM, LRHE_ENOMEM, LRHE_EAGAIN, LRHE_EDEVICE, LRHE_ENOISE = 0, -1, -2, -3, -4, -5, -6
 WIRE_CT, WIRE_GK, WIRE_PK, WIRE_SK = 1, 2, 3, 4
