@@ -113,6 +113,25 @@ def counted_traffic(le_mac, mac_mode):
     return int(float(kv["traffic_bytes_per_launch"]))
 
 
+TUNE_CACHE = os.environ.get("LRHE_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "lrhe", "tune.txt")
+
+
+def tune_key(ctx, torch):
+    """Cache key of a context's launch choices: GPU architecture, ring, moduli count,
+    plaintext modulus and a digest of the kernel sources (a kernel change retunes)."""
+    arch = torch.cuda.get_device_properties(ctx.device).gcnArchName.split(":")[0]
+    return f"{arch}/n{ctx.n}/L{ctx.L}/t{ctx.t}/{kernel_source_digest()[:16]}"
+
+
+def tune_from_cache(ctx, torch, args) -> bool:
+    return not args.retune and ctx.tune_load(TUNE_CACHE, tune_key(ctx, torch))
+
+
+def tune_to_cache(ctx, torch):
+    os.makedirs(os.path.dirname(TUNE_CACHE), exist_ok=True)
+    ctx.tune_save(TUNE_CACHE, tune_key(ctx, torch))
+
+
 def cpu_baseline(pname, rows, f, classes, seed):
     """The oracle as it stands, on a bounded sample of the same workload, and on
     the whole single-individual workload (1 x 40,000 x 16)."""
@@ -276,8 +295,9 @@ def bench_paper_point(P, WL, O, torch, args):
         y = ctx.empty_ct(-(-wl.rows * wl.classes // ctx.n))
         ws = ctx.workspace(P.native.WS_MATMUL_FAST, wl.rows, wl.f, wl.classes)
         ctx.encrypt_rows(keys, Xd, seed=32, out=xct, ws=ws_enc)
-        if not args.no_autotune:
+        if not args.no_autotune and not tune_from_cache(ctx, torch, args):
             ctx.autotune_fast(keys, model, xct, wl.rows, out=y, ws=ws)
+            tune_to_cache(ctx, torch)
         sides.append((ctx, keys, model, xct, ws_enc, y, ws))
 
     def run():
@@ -516,6 +536,7 @@ def main():
     ap.add_argument("--features", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--retune", action="store_true", help="autotune even where the tuning cache has an entry")
     ap.add_argument("--tune", default="", metavar="KEY=V,...",
                     help="set launch choices (e.g. large.le_mac=6,large.mac_mode=0) instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -569,7 +590,13 @@ def main():
         key, val = kv.split("=")
         ctx.tune_set(key.strip(), int(val))
     fixed = args.no_autotune or bool(args.tune)
-    tuned = ctx.tuning() if fixed else ctx.autotune_fast(keys, model, xct, rows, out=y, ws=ws)
+    # launch choices: as given, from the tuning cache, or autotuned (both tile
+    # classes: this job's tiles here, the single inference's below) and cached
+    cached = not fixed and tune_from_cache(ctx, torch, args)
+    tuning_source = "fixed" if fixed else ("cache" if cached else "autotuned")
+    tuned = ctx.tuning() if fixed or cached else ctx.autotune_fast(keys, model, xct, rows, out=y, ws=ws)
+    if not fixed and not cached and args.no_extras:
+        tune_to_cache(ctx, torch)
     log("tuning", tuned)
 
     def step():
@@ -666,8 +693,9 @@ def main():
         s1 = one_fast()
         assert np.array_equal(s1, O.plain_scores(w1.X, w1.W, w1.b, p.t))
         # the latency-bound tile class (16 pairs) keeps its own launch choices
-        if not fixed:
+        if not fixed and not cached:
             ctx.autotune_fast(keys, m1, x1, 1, out=y1, ws=ws1)
+            tune_to_cache(ctx, torch)
         fast_ms = timeit(one_fast, 5)
         fast_srv_ms = timeit(lambda: ctx.matmul_fast(keys, m1, x1, 1, out=y1, ws=ws1), 5)
         fct = ctx.empty_ct(w1.f)
@@ -749,7 +777,7 @@ def main():
         "server_inferences_per_s": round(server_rate, 3),
         "noise_budget_bits": round(budget, 1),
         "roofline": roofline,
-        "tuning": ctx.tuning(),
+        "tuning": ctx.tuning(), "tuning_source": tuning_source,
         "kernels": kern,
         **extras,
         "paper_context": "Threadripper 3960X, SEAL, n=8192, 11 classes: 543 patients in 46.77 s total "

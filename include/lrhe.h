@@ -357,6 +357,17 @@ int lrhe_tune_get(const lrhe_ctx* ctx, const char* key, int* value);
 int lrhe_autotune_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct, uint32_t rows,
                        uint32_t* y_out, void* ws, size_t ws_bytes, void* stream, int reps);
 
+/* Tuning cache: lrhe_tune_save writes the context's launch choices (both tile
+ * classes, "tile", "small_below") to the text file `path` under `key`, one
+ * line per key, replacing that key's line and keeping the others.  The key is
+ * the caller's (for example GPU architecture, ring dimension, number of primes
+ * and a digest of the kernel sources).  lrhe_tune_load applies the key's
+ * choices: LRHE_OK when found, LRHE_EAGAIN (not an error) when the file or
+ * the key is absent, EINVAL for a malformed entry or a choice unavailable at
+ * this ring dimension (the context keeps its choices then). */
+int lrhe_tune_save(const lrhe_ctx* ctx, const char* path, const char* key);
+int lrhe_tune_load(lrhe_ctx* ctx, const char* path, const char* key);
+
 /* Opt-in kernel timing: while enabled, every kernel launch of the library is
  * bracketed by HIP events on its own stream.  lrhe_prof_get returns the number
  * of launches and their summed duration (ms) for a kernel name (for example

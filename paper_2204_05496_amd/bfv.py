@@ -325,6 +325,17 @@ class Context:
         N.check(N.lib().lrhe_tune_get(self.h, key.encode(), ctypes.byref(v)))
         return v.value
 
+    def tune_save(self, path: str, key: str):
+        N.check(N.lib().lrhe_tune_save(self.h, path.encode(), key.encode()))
+
+    def tune_load(self, path: str, key: str) -> bool:
+        """Apply a cached entry; False when the file or key is absent."""
+        rc = N.lib().lrhe_tune_load(self.h, path.encode(), key.encode())
+        if rc == N.LRHE_EAGAIN:
+            return False
+        N.check(rc)
+        return True
+
     def tuning(self) -> dict:
         names = ("le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt")
         return {"large": {k: self.tune_get("large." + k) for k in names},

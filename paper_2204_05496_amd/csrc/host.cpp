@@ -1286,6 +1286,74 @@ extern "C" int lrhe_tune_get(const lrhe_ctx* c, const char* key, int* value) {
   return LRHE_OK;
 }
 
+// ------------------------------------------------------------------ tuning cache
+// One line per key: "<key>\t<name>=<value> <name>=<value> ..." with the names of
+// lrhe_tune_get (both classes, tile, small_below).
+static const char* const k_tune_names[] = {"le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt"};
+
+extern "C" int lrhe_tune_save(const lrhe_ctx* c, const char* path, const char* key) {
+  if (!c || !path || !key) return fail(LRHE_EINVAL, "null argument");
+  if (!*key || std::strpbrk(key, "\t\n")) return fail(LRHE_EINVAL, "tuning key must be non-empty, no tab or newline");
+  std::string line = std::string(key) + "\t";
+  for (const char* cls : {"small.", "large."})
+    for (const char* nm : k_tune_names) {
+      std::string k = std::string(cls) + nm;
+      int v = 0;
+      lrhe_tune_get(c, k.c_str(), &v);
+      line += k + "=" + std::to_string(v) + " ";
+    }
+  line += "tile=" + std::to_string(c->tune.tile) + " small_below=" + std::to_string(c->tune.small_below);
+  // keep the other keys' lines, replace this key's
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path, "r")) {
+    char buf[4096];
+    while (std::fgets(buf, sizeof(buf), f)) {
+      std::string l(buf);
+      while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+      if (l.empty() || l.compare(0, std::strlen(key) + 1, std::string(key) + "\t") == 0) continue;
+      keep.push_back(l);
+    }
+    std::fclose(f);
+  }
+  keep.push_back(line);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(LRHE_EINVAL, "cannot write %s", tmp.c_str());
+  for (const auto& l : keep) std::fprintf(f, "%s\n", l.c_str());
+  const bool ok = std::fclose(f) == 0 && std::rename(tmp.c_str(), path) == 0;
+  return ok ? LRHE_OK : fail(LRHE_EINVAL, "cannot write %s", path);
+}
+
+extern "C" int lrhe_tune_load(lrhe_ctx* c, const char* path, const char* key) {
+  if (!c || !path || !key) return fail(LRHE_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return LRHE_EAGAIN;
+  std::string found;
+  char buf[4096];
+  const std::string pre = std::string(key) + "\t";
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string l(buf);
+    if (l.compare(0, pre.size(), pre) == 0) found = l.substr(pre.size());
+  }
+  std::fclose(f);
+  if (found.empty()) return LRHE_EAGAIN;
+  // apply to a copy, so that a bad entry leaves the context as it was
+  const lrhe::Tune before = c->tune;
+  size_t pos = 0;
+  int rc = LRHE_OK;
+  while (rc == LRHE_OK && pos < found.size()) {
+    const size_t end = found.find_first_of(" \n\r", pos);
+    const std::string tok = found.substr(pos, end == std::string::npos ? std::string::npos : end - pos);
+    pos = end == std::string::npos ? found.size() : end + 1;
+    if (tok.empty()) continue;
+    const size_t eq = tok.find('=');
+    if (eq == std::string::npos) { rc = fail(LRHE_EINVAL, "tuning cache: bad entry '%s'", tok.c_str()); break; }
+    rc = lrhe_tune_set(c, tok.substr(0, eq).c_str(), std::atoi(tok.c_str() + eq + 1));
+  }
+  if (rc != LRHE_OK) c->tune = before;
+  return rc;
+}
+
 extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_model* m, const uint32_t* xct,
                                   uint32_t rows, uint32_t* y_out, void* ws, size_t ws_bytes, void* stream, int reps) {
   if (!c || !gk || !m || !xct || !y_out) return fail(LRHE_EINVAL, "null argument");

@@ -103,6 +103,8 @@ SIGNATURES = {
     "lrhe_tune_set": (i32, [vp, ctypes.c_char_p, i32]),
     "lrhe_tune_get": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(i32)]),
     "lrhe_autotune_fast": (i32, [vp, vp, vp, vp, u32, vp, vp, sz, vp, i32]),
+    "lrhe_tune_save": (i32, [vp, ctypes.c_char_p, ctypes.c_char_p]),
+    "lrhe_tune_load": (i32, [vp, ctypes.c_char_p, ctypes.c_char_p]),
     "lrhe_prof_enable": (None, [i32]),
     "lrhe_prof_reset": (None, []),
     "lrhe_prof_get": (i32, [ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]),

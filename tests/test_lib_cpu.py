@@ -176,3 +176,36 @@ def test_fast_workspace_accumulator_slots(P):
     for below, extra in ((33, 0), (40, 78 - 64), (64, 126 - 64)):
         ctx.tune_set("small_below", below)
         assert size(100) - base == extra * slot, below
+
+
+def test_tuning_cache_round_trip(P, tmp_path):
+    """lrhe_tune_save / lrhe_tune_load: a key's choices come back into a new
+    context, other keys in the file are kept, an absent key or file is not an
+    error, and a bad entry is refused without touching the context."""
+    p = WL.PARAMS["n16k"]
+    path = str(tmp_path / "tune.txt")
+    a = P.Context.from_params(p, device=-1)
+    assert not a.tune_load(path, "gfx950/n16384/L7/x")            # no file yet
+    a.tune_set("large.le_mac", 5)
+    a.tune_set("large.mac_mode", 2)
+    a.tune_set("small.le_intt", 6)
+    a.tune_set("tile", 2048)
+    a.tune_save(path, "gfx950/n16384/L7/x")
+    b = P.Context.from_params(p, device=-1)
+    b.tune_set("large.le_mask", 6)
+    b.tune_save(path, "gfx950/n16384/L7/y")
+    c = P.Context.from_params(p, device=-1)
+    assert c.tune_load(path, "gfx950/n16384/L7/x") and c.tuning() == a.tuning()
+    assert c.tune_load(path, "gfx950/n16384/L7/y") and c.tuning() == b.tuning()
+    assert not c.tune_load(path, "gfx950/n16384/L7/z")
+    assert sum(1 for _ in open(path)) == 2
+    a.tune_set("large.le_mac", 6)
+    a.tune_save(path, "gfx950/n16384/L7/x")                       # replaces its own line only
+    assert sum(1 for _ in open(path)) == 2
+    assert c.tune_load(path, "gfx950/n16384/L7/x") and c.tuning()["large"]["le_mac"] == 6
+    with open(path, "a") as fh:
+        fh.write("bad\tlarge.le_mac=9 large.mac_mode=1\n")
+    before = c.tuning()
+    with pytest.raises(P.native.LrheError):
+        c.tune_load(path, "bad")
+    assert c.tuning() == before
