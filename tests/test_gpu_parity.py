@@ -211,6 +211,33 @@ def test_single_40k_standard(n16k, torch):
     assert np.array_equal(n16k.coeff(ctx.matmul_standard(ms, fct)), o.standard_matmul(fo, Ws, wl.b))
 
 
+@pytest.mark.parametrize("cls", ["small", "large"])
+@pytest.mark.parametrize("stage", [1, 2 + 1, 2 + 7, 2 + 14, 100, 0])
+def test_stage_parity_n16k(n16k, torch, stage, cls):
+    """Per-pair ciphertext after each stage at n = 16384, L = 7 (1 x 40,000 x 16):
+    chunk products (1), 1, 7 and all 14 rotate-and-accumulate steps, bias (100)
+    and mask (0), with the small-tile kernels (digit halves) and with the
+    large-tile ones (the same 16 pairs run as a large tile); three pairs each
+    against the oracle."""
+    wl = WL.single()
+    ctx, o = n16k.ctx, n16k.o
+    say("stage", stage, cls)
+    keep = ctx.tune_get("small_below")
+    if cls == "large":
+        ctx.tune_set("small_below", 1)
+    try:
+        xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=17)
+        model = ctx.model(wl.W, wl.b)
+        got = n16k.coeff(ctx.matmul_fast_pairs(n16k.keys, model, xct, wl.rows, 0, wl.rows * wl.classes, stage))
+    finally:
+        ctx.tune_set("small_below", keep)
+    xo = o.encrypt_rows(n16k.ko, wl.X, seed=17)
+    wo = o.encode_weights(wl.W)
+    for r in (0, 7, 15):
+        ref = o.pair(n16k.ko, xo[0], wo[r], int(wl.b[r]), r % o.n, stage)
+        assert np.array_equal(got[r], ref), f"pair {r} stage {stage} ({cls} tiles)"
+
+
 def test_batch_512x40k_launch_config(n16k, torch):
     """512 individuals x 40,000 features (the throughput workload) in the launch
     configuration the benchmark times: the whole output ciphertext equals the
