@@ -332,7 +332,11 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * order), the special-prime inverse transforms in a kernel of their own
  * and the division by P split by ciphertext part (more workgroups for tiles
  * too small to fill the GPU; small class only, EINVAL for the large class or
- * a bare key); "fuse_intt" = 1 lets the rounded division by P of each
+ * a bare key); 5: one exchange buffer, two workgroups per CU and the next
+ * stage's twiddles loaded ahead, with the target moduli spread by XCD: in each
+ * window of 256 pairs an XCD takes two of the eight moduli for half of the
+ * pairs, so its L2 holds a quarter of the step's Galois key (needs L = 7 and
+ * an even tile; otherwise the plain launch order); "fuse_intt" = 1 lets the rounded division by P of each
  * rotation step also compute the next step's digits (inverse transform of the
  * automorphism of c1), so the digit kernel runs on the first step only; 0
  * (default) runs it on every step; ignored by variant 4.  These six keys exist

@@ -508,7 +508,8 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // products accumulate unreduced 64-bit products (one multiply-add each, folded
 // every 4 digits) instead of reducing every product; 256 = two workgroups per
 // item, one for each half of the digits, writing their sums to ACC and ACC2
-// (canonical, no inverse transform for r = P; k_ks_rho finishes that item).
+// (canonical, no inverse transform for r = P; k_ks_rho finishes that item);
+// 512 = target moduli by XCD (below).
 template <int LOGN, int LE, int MODE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
     DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
@@ -531,13 +532,33 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
   }
   constexpr bool HALF = (MODE & 256) != 0;
   const int per_pair = HALF ? 2 * (L + 1) : L + 1;   // workgroups per pair
-  const size_t lp = li / per_pair;
+  size_t lp = li / per_pair;
   const int wi = (int)(li % per_pair);
   // the special-prime item (r = L) carries more work than the others; MODE 32
   // rotates its place among the pair's workgroups from pair to pair, so the
   // heavy items spread over the launch order
   int r = HALF ? wi >> 1 : wi;
   if constexpr ((MODE & 32) != 0) r = (r + (int)(lp % (L + 1))) % (L + 1);
+  if constexpr ((MODE & 512) != 0) {
+    static_assert((MODE & (64 | 256)) == 0, "MODE 512 replaces the pair-per-XCD order and has one item per workgroup");
+    // Eight target moduli (L = 7) on eight XCDs.  XCD x runs the workgroups
+    // x, x + 8, ...; its s-th one is slot s.  The slots of each XCD are cut into
+    // windows of KW pairs; in window w, XCD x takes the moduli 2m and 2m + 1,
+    // m = (x + w) mod 4, for one half of the window's pairs (the half x / 4),
+    // a pair's two workgroups in adjacent slots.  An XCD's L2 then holds two
+    // key slices of the step instead of all eight, and the special prime
+    // moves to other XCDs from window to window.  Every (pair, modulus) is
+    // taken once: per window the four values of m meet both halves.
+    constexpr uint32_t KW = 256;
+    const uint32_t npairs = gridDim.x / 8;
+    if (L == 7 && (npairs & 1) == 0) {
+      const uint32_t x = blockIdx.x % 8, s = blockIdx.x / 8;
+      const uint32_t w = s / KW, k = s % KW, p0 = w * KW;
+      const uint32_t wl = min(KW, npairs - p0);   // pairs in this window, even
+      lp = p0 + (x / 4) * (wl / 2) + k / 2;
+      r = (int)(2 * ((x + w) % 4) + (k & 1));
+    }
+  }
   // digits of this workgroup: all of them, or one half
   const int half = HALF ? wi & 1 : 0;
   const int i_lo = half ? (L + 1) / 2 : 0;

@@ -32,7 +32,8 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
   LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
   LRHE_MAC_MODE_CASE(2, LN, LE, 225) /* double buffer, pair per XCD, rotated, 64-bit MAC */   \
   LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */                           \
-  LRHE_MAC_MODE_CASE(4, LN, LE, 385) /* double buffer, 64-bit MAC, two workgroups per item (digit halves) */
+  LRHE_MAC_MODE_CASE(4, LN, LE, 385) /* double buffer, 64-bit MAC, two workgroups per item (digit halves) */ \
+  LRHE_MAC_MODE_CASE(5, LN, LE, 524) /* one buffer, 2 workgroups/CU, twiddle prefetch, moduli by XCD */
 #endif
 
 template <int LN>

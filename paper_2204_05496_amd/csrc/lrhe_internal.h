@@ -74,7 +74,7 @@ namespace lrhe {
 // Launch choices of the fast-matmul kernels (set by lrhe_tune_set / lrhe_autotune_fast):
 // log2 of the residues per thread of each transform kernel, pairs per tile.
 #ifndef LRHE_MAC_NMODES
-#define LRHE_MAC_NMODES 5   // k_ks_mac variants behind the "mac_mode" tuning key
+#define LRHE_MAC_NMODES 6   // k_ks_mac variants behind the "mac_mode" tuning key
 #endif
 // the variant that splits each key-switch item's digits over two workgroups
 // (latency of small tiles); it needs two accumulator slots per tile pair, so

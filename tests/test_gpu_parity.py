@@ -211,26 +211,31 @@ def test_single_40k_standard(n16k, torch):
     assert np.array_equal(n16k.coeff(ctx.matmul_standard(ms, fct)), o.standard_matmul(fo, Ws, wl.b))
 
 
-@pytest.mark.parametrize("cls", ["small", "large"])
+@pytest.mark.parametrize("cls", ["small", "large", "large_xcd"])
 @pytest.mark.parametrize("stage", [1, 2 + 1, 2 + 7, 2 + 14, 100, 0])
-def test_stage_parity_n16k(n16k, torch, stage, cls):
+def test_stage_parity_n16k(n16k, torch, P, stage, cls):
     """Per-pair ciphertext after each stage at n = 16384, L = 7 (1 x 40,000 x 16):
     chunk products (1), 1, 7 and all 14 rotate-and-accumulate steps, bias (100)
-    and mask (0), with the small-tile kernels (digit halves) and with the
-    large-tile ones (the same 16 pairs run as a large tile); three pairs each
-    against the oracle."""
+    and mask (0), with the small-tile kernels (digit halves), with the
+    large-tile ones (the same 16 pairs run as a large tile) and with the
+    large-tile inner-product variant that spreads the target moduli by XCD;
+    three pairs each against the oracle."""
     wl = WL.single()
     ctx, o = n16k.ctx, n16k.o
     say("stage", stage, cls)
     keep = ctx.tune_get("small_below")
-    if cls == "large":
+    keep_mode = ctx.tune_get("large.mac_mode")
+    if cls != "small":
         ctx.tune_set("small_below", 1)
+    if cls == "large_xcd":
+        ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD)
     try:
         xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=17)
         model = ctx.model(wl.W, wl.b)
         got = n16k.coeff(ctx.matmul_fast_pairs(n16k.keys, model, xct, wl.rows, 0, wl.rows * wl.classes, stage))
     finally:
         ctx.tune_set("small_below", keep)
+        ctx.tune_set("large.mac_mode", keep_mode)
     xo = o.encrypt_rows(n16k.ko, wl.X, seed=17)
     wo = o.encode_weights(wl.W)
     for r in (0, 7, 15):
@@ -281,4 +286,29 @@ def test_batch_512x40k_launch_config(n16k, torch):
     q = torch.tensor(list(n16k.p.q), dtype=torch.int64, device=allp.device).view(1, -1, 1)
     assert torch.equal(acc % q, y[0].to(torch.int64))
     del allp, acc
+    torch.cuda.empty_cache()
+
+
+def test_batch_512x40k_moduli_by_xcd(n16k, torch, P):
+    """The throughput workload with the inner-product variant that gives each
+    XCD two target moduli per window of pairs (its own workgroup-to-item map):
+    the whole output ciphertext equals the oracle's stored one."""
+    import golden_ref
+    wl = WL.batch()
+    ctx = n16k.ctx
+    keep = ctx.tune_get("large.mac_mode")
+    ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD)
+    try:
+        say("batch encrypt")
+        xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=3)
+        model = ctx.model(wl.W, wl.b)
+        say("batch fast, moduli by XCD")
+        y = ctx.matmul_fast(n16k.keys, model, xct, wl.rows)
+        torch.cuda.synchronize()
+    finally:
+        ctx.tune_set("large.mac_mode", keep)
+    ref = golden_ref.load("batch_512x40000x16_fast_output.txt")[wl.name]
+    bad = golden_ref.mismatches(n16k.coeff(y), ref)
+    assert not bad, f"{len(bad)} limbs differ from the oracle, first {bad[0][:3]}"
+    del y
     torch.cuda.empty_cache()
