@@ -107,18 +107,36 @@ __device__ __forceinline__ uint32_t auto_perm(uint32_t k, uint32_t g, int logn) 
 // write-after-read barrier is not needed, because consecutive exchanges use
 // different buffers and the barrier of the exchange in between orders them.
 // Addresses: one padded per-thread base per side, constant element offsets.
+//
+// The boundary next to the last pass of a WLAST geometry stays inside each
+// wave: the wave reads back only the block it wrote, so a wave-scope fence
+// replaces the barrier after the writes (one wave's LDS operations execute in
+// program order).  Forward direction (pto = last pass): the block was last read,
+// since the previous barrier, by its own wave only (the exchange into pass
+// NPASS - 2 is block-local on its read side), so the barrier before the writes
+// goes too.  Inverse direction (pfrom = last pass): this is the transform's first
+// exchange and may follow reads of the whole buffer by every wave (a gather, an
+// earlier transform), so that barrier stays.  Single-buffered only: the
+// double-buffered order relies on every exchange having its barrier.
 template <class G, bool DB = false>
 __device__ __forceinline__ void xchg(uint32_t* lds, int pfrom, int pto, uint32_t* x, int t, int* par = nullptr) {
+  const bool wave_local = !DB && G::WLAST && (pfrom == G::NPASS - 1 || pto == G::NPASS - 1);
   if constexpr (DB) {
     lds += (*par) * G::LDS_WORDS;
     *par ^= 1;
   } else {
-    __syncthreads();
+    if (!(wave_local && pto == G::NPASS - 1)) __syncthreads();
   }
   uint32_t* wr = lds + G::pad(G::tbase(pfrom, t));
 #pragma unroll
   for (int e = 0; e < G::E; ++e) wr[G::padoff(G::eoff(pfrom, e))] = x[e];
-  __syncthreads();
+  if (wave_local) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
   const uint32_t* rd = lds + G::pad(G::tbase(pto, t));
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = rd[G::padoff(G::eoff(pto, e))];
@@ -515,8 +533,10 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
     DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
     const uint32_t* __restrict__ gk_default, uint32_t gi, uint32_t g, uint32_t* __restrict__ ACC,
     uint32_t* __restrict__ ACC2) {
-  using G = Geom<LOGN, LE>;
-  constexpr bool DB = (MODE & 1) && 2 * G::LDS_WORDS * 4 <= 160 * 1024;
+  constexpr bool DB = (MODE & 1) && 2 * Geom<LOGN, LE>::LDS_WORDS * 4 <= 160 * 1024;
+  // the wave-local last-pass blocks only pay where they remove barriers
+  // (single buffer); double-buffered, the plain numbering measured faster
+  using G = Geom<LOGN, LE, !DB>;
   constexpr bool DP = (MODE & 2) != 0;   // digit prefetch
   constexpr bool PF = (MODE & 4) != 0;   // twiddle prefetch
   constexpr bool A64 = (MODE & 128) != 0;
@@ -846,7 +866,9 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const ui
                                                              const PairDesc* __restrict__ pairs,
                                                              const GroupDesc* __restrict__ groups, int mode,
                                                              uint32_t* __restrict__ out) {
-  using Gg = Geom<LOGN, LE>;
+  // the sub-problem numbering of the last pass without the wave-local blocks:
+  // this kernel's last-pass loads and stores measured faster with it
+  using Gg = Geom<LOGN, LE, false>;
   __shared__ uint32_t lds[Gg::LDS_WORDS];
   const int L = c.L;
   const GroupDesc grp = groups[blockIdx.x / L];

@@ -73,24 +73,40 @@ LRHE_HD uint32_t brv(uint32_t x, int bits) {
 // E = 2^LOGE per thread.  The LOGN stages are cut into passes of LOGE stages
 // (the last pass may be shorter).  In pass p (stages s0 .. s0 + r - 1) the
 // array splits into independent sub-problems of 2^r elements with stride
-// n >> (s0 + r); thread t owns sub-problems sp = u T + t, u < E >> r.
+// n >> (s0 + r); thread t owns the sub-problems sp(p, t, u), u < E >> r:
+// sp = u T + t, except in the last pass of a multi-wave transform of three or
+// more passes when WL is set (WLAST).  There the lane (t mod 64) takes the low
+// bits of sp, u the next ones and the wave (t / 64) the top ones, so each wave
+// owns one contiguous block of 64 E residues, the same block it owns in the
+// pass before: that boundary is crossed without a workgroup barrier.  The
+// numbering only changes which thread holds which residue in registers; global
+// data keeps its natural order, so kernels may choose WL independently.
 // ---------------------------------------------------------------------------
-template <int LOGN_, int LOGE_>
+template <int LOGN_, int LOGE_, bool WL = true>
 struct Geom {
   static constexpr int LOGN = LOGN_, LOGE = LOGE_;
   static constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N >> LOGE;
   static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
+  static constexpr int LOGT = LOGN - LOGE;
+  static constexpr bool WLAST = WL && NPASS >= 3 && LOGT > 6;
+  static constexpr int LOGNU_LAST = LOGE - (LOGN - (NPASS - 1) * LOGE);   // log2 (E >> r) in the last pass
   // padded exchange buffer: one pad word per 2^PADSH words keeps every wave's
   // exchange accesses free of LDS bank conflicts (64 banks, 32 lanes per cycle)
   static constexpr int PADSH = LOGE == 4 ? 3 : LOGE;
   static constexpr int LDS_WORDS = N + (N >> PADSH);
   LRHE_HD static constexpr int s0(int p) { return p * LOGE; }
   LRHE_HD static constexpr int r(int p) { return (LOGN - p * LOGE) < LOGE ? (LOGN - p * LOGE) : LOGE; }
+  // sub-problem u of thread t in pass p
+  LRHE_HD static uint32_t sp(int p, int t, uint32_t u) {
+    const uint32_t ut = (uint32_t)t;
+    if (WLAST && p == NPASS - 1) return (ut & 63u) | (u << 6) | ((ut >> 6) << (6 + LOGNU_LAST));
+    return u * T + ut;
+  }
   // global index of element e (= u 2^r + c) of thread t in pass p
   LRHE_HD static uint32_t idx(int p, int t, int e) {
     const int rr = r(p), sh = s0(p);
     const uint32_t c = (uint32_t)e & ((1u << rr) - 1), u = (uint32_t)e >> rr;
-    const uint32_t sp = u * T + (uint32_t)t;
+    const uint32_t sp = Geom::sp(p, t, u);
     const int lstride = LOGN - sh - rr;   // log2 of the stride
     const uint32_t h = sp >> lstride, l = sp & ((1u << lstride) - 1);
     return (h << (LOGN - sh)) + (c << lstride) + l;
@@ -101,12 +117,16 @@ struct Geom {
   // (h field, stride field, low field; T is a multiple of the stride), so also
   // pad(idx) = pad(tbase) + padoff(eoff): one per-thread base and a
   // compile-time offset per element.
+  // (the last pass has stride 1: index = sp 2^r + c; under WLAST its lane and
+  // wave fields are per thread, u and c per element)
   LRHE_HD static uint32_t tbase(int p, int t) {
     const int ls = LOGN - s0(p) - r(p);
     const uint32_t ut = (uint32_t)t;
+    if (WLAST && p == NPASS - 1) return ((ut & 63u) | ((ut >> 6) << (6 + LOGNU_LAST))) << r(p);
     return ((ut >> ls) << (LOGN - s0(p))) + (ut & ((1u << ls) - 1));
   }
   LRHE_HD static constexpr uint32_t eoff(int p, int e) {
+    if (WLAST && p == NPASS - 1) return (((uint32_t)(e >> r(p)) << 6) << r(p)) + ((uint32_t)e & ((1u << r(p)) - 1));
     return ((((uint32_t)(e >> r(p)) * (uint32_t)T) >> (LOGN - s0(p) - r(p))) << (LOGN - s0(p))) +
            (((uint32_t)e & ((1u << r(p)) - 1)) << (LOGN - s0(p) - r(p)));
   }
@@ -128,7 +148,7 @@ template <class G, class TW>
 LRHE_HD void stage_tw(int p, int t, int u, int tau, const TW& tw, uint32_t* w) {
   const int rr = G::r(p), sh = G::s0(p);
   const int lstride = G::LOGN - sh - rr;
-  const int h = sh == 0 ? u : (u * G::T + t) >> lstride;
+  const int h = sh == 0 ? u : (int)(G::sp(p, t, (uint32_t)u) >> lstride);
   // a fixed trip count, so the loop unrolls before tau is known; the guards
   // fold once the callers' stage loops are unrolled
 #pragma unroll
@@ -159,7 +179,7 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint3
         if (more) stage_tw<G>(p, t, tau + 1 < rr ? u : u + 1, tau + 1 < rr ? tau + 1 : 0, tw, wn);
       }
       const int half = 1 << (rr - 1 - tau);
-      const int h = G::s0(p) == 0 ? u : (u * G::T + t) >> (G::LOGN - G::s0(p) - rr);
+      const int h = G::s0(p) == 0 ? u : (int)(G::sp(p, t, (uint32_t)u) >> (G::LOGN - G::s0(p) - rr));
 #pragma unroll
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
@@ -209,7 +229,7 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint
         if (more) stage_tw<G>(p, t, tau > 0 ? u : u + 1, tau > 0 ? tau - 1 : rr - 1, itw, wn);
       }
       const int half = 1 << (rr - 1 - tau);
-      const int h = G::s0(p) == 0 ? u : (u * G::T + t) >> (G::LOGN - G::s0(p) - rr);
+      const int h = G::s0(p) == 0 ? u : (int)(G::sp(p, t, (uint32_t)u) >> (G::LOGN - G::s0(p) - rr));
 #pragma unroll
       for (int c = 0; c < (1 << rr); ++c) {
         if (c & half) continue;
