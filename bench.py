@@ -84,6 +84,17 @@ def ks_mac_modmuls(n, L, pairs):
     return pairs * (L * per_q + per_p)
 
 
+def ks_mac_md_modmuls(n, L, pairs):
+    """Algorithmic modular multiplications of one k_ks_mac_md launch (the split
+    variant's data-modulus items) over `pairs` ciphertexts.  Per item r: the L - 1
+    digit transforms and 2 L n inner-product products as in k_ks_mac, then the
+    rounded division by P: rho's two parts transformed mod q_r and 2 n products
+    by P^-1."""
+    logn = int(np.log2(n))
+    ntt = (n // 2) * logn
+    return pairs * L * ((L - 1) * ntt + 2 * L * n + 2 * ntt + 2 * n)
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ks_mac_traffic_batch_512x40000x16_le{le}_mode{mode}.txt")
 KERNEL_SOURCES = ("kernels_dev.h", "ks_step.hip", "kernels.hip", "lrhe_math.h", "lrhe_internal.h")
 
@@ -637,20 +648,22 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = rows * args.steps / dt
     kern = {}
-    for name in ("k_ks_mac", "k_ks_intt", "k_ks_rho", "k_ks_moddown", "k_mac", "k_mask", "k_compress", "k_encrypt", "k_encode",
-                 "k_sample"):
+    for name in ("k_ks_mac", "k_ks_mac_p", "k_ks_mac_md", "k_ks_intt", "k_ks_rho", "k_ks_moddown", "k_mac", "k_mask",
+                 "k_compress", "k_encrypt", "k_encode", "k_sample"):
         c, ms = prof_get(lib, name)
         kern[name] = {"launches": c, "avg_ms": ms / c if c else None, "total_ms_per_step": ms / args.steps}
     log("step ms", ms_step, "kernels", json.dumps(kern))
 
     # roofline of the dominant kernel (key-switch digit transforms + inner product)
     lay_B = min(4096, rows * classes)
-    c_mac, ms_mac = prof_get(lib, "k_ks_mac")
+    # the split variant's dominant kernel is its data-modulus launch
+    split = tuned["large"]["mac_mode"] == P.native.MAC_MODE_SPLIT
+    mac_name = "k_ks_mac_md" if split else "k_ks_mac"
+    c_mac, ms_mac = prof_get(lib, mac_name)
     avg_ms = ms_mac / max(c_mac, 1)
-    per_launch = ks_mac_modmuls(ctx.n, ctx.L, lay_B) if rows * classes >= 4096 else ks_mac_modmuls(ctx.n, ctx.L,
-                                                                                                 rows * classes)
+    per_launch = (ks_mac_md_modmuls if split else ks_mac_modmuls)(ctx.n, ctx.L, lay_B)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_ks_mac", "achieved": round(achieved, 3), "peak": round(MODMUL_PEAK_T, 3),
+    roofline = {"bound": "alu", "kernel": mac_name, "achieved": round(achieved, 3), "peak": round(MODMUL_PEAK_T, 3),
                 "unit": "Tmodmul/s", "frac": round(achieved / MODMUL_PEAK_T, 4),
                 "traffic": counted_traffic(tuned["large"]["le_mac"], tuned["large"]["mac_mode"]) if rows * classes >= 4096 else None,
                 "avg_launch_ms": round(avg_ms, 4), "modmul_per_launch": per_launch}

@@ -336,16 +336,22 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * stage's twiddles loaded ahead, with the target moduli spread by XCD: in each
  * window of 256 pairs an XCD takes two of the eight moduli for half of the
  * pairs, so its L2 holds a quarter of the step's Galois key (needs L = 7 and
- * an even tile; otherwise the plain launch order); "fuse_intt" = 1 lets the rounded division by P of each
+ * an even tile; otherwise the plain launch order); 6: two launches per
+ * rotation step, the special-prime items first (at "le_mac_p" residues per
+ * thread), then the data-modulus items, each of which also does the rounded
+ * division by P and the rotate-and-accumulate of its limb from the sums in its
+ * registers, so no k_ks_moddown runs and no sum of a data modulus goes through
+ * memory; "le_mac_p" = residues per thread of that special-prime launch;
+ * "fuse_intt" = 1 lets the rounded division by P of each
  * rotation step also compute the next step's digits (inverse transform of the
  * automorphism of c1), so the digit kernel runs on the first step only; 0
- * (default) runs it on every step; ignored by variant 4.  These six keys exist
+ * (default) runs it on every step; ignored by variants 4 and 6.  These seven keys exist
  * in two classes, for tiles of fewer than
  * "small_below" pairs (default 64; such launches are latency-bound) and for
  * larger tiles: "small.<key>" and "large.<key>" address one class, a bare key
  * sets both and reads the large class.  Defaults: large tiles le_intt 5,
  * le_mac 6, le_moddown 6, le_mask 4 (each 5 where the ring dimension does not
- * allow it) and mac_mode 1; small tiles le_intt 5, le_mac, le_moddown and
+ * allow it), mac_mode 6 and le_mac_p 5; small tiles le_intt 5, le_mac, le_moddown and
  * le_mask 4 (5 where not available) and mac_mode 4.
  * "tile" = pairs per tile (default 4096), "small_below" as above; the
  * workspace size depends on both (small tiles hold two accumulators per pair).

@@ -337,7 +337,7 @@ class Context:
         return True
 
     def tuning(self) -> dict:
-        names = ("le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt")
+        names = ("le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt", "le_mac_p")
         return {"large": {k: self.tune_get("large." + k) for k in names},
                 "small": {k: self.tune_get("small." + k) for k in names},
                 "tile": self.tune_get("tile"), "small_below": self.tune_get("small_below")}

@@ -328,7 +328,10 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
   c->tune.large.le_mac = le_valid(c->logn, 6) ? 6 : 5;
   c->tune.large.le_moddown = le_valid(c->logn, 6) ? 6 : 5;
   c->tune.large.le_mask = le_valid(c->logn, 4) ? 4 : 5;
-  c->tune.large.mac_mode = 1;
+  // the split variant: special-prime items at 32 residues per thread, then the
+  // data-modulus items (with the division by P) at 64
+  c->tune.large.mac_mode = LRHE_MAC_MODE_SPLIT;
+  c->tune.large.le_mac_p = 5;
   // and for small tiles, as measured on a single inference (16 pairs): the
   // digit-halves variant at 16 residues per thread
   c->tune.small.le_intt = 5;
@@ -336,6 +339,7 @@ extern "C" int lrhe_ctx_create(const lrhe_params* p, int device, lrhe_ctx** out)
   c->tune.small.le_moddown = le_valid(c->logn, 4) ? 4 : 5;
   c->tune.small.le_mask = le_valid(c->logn, 4) ? 4 : 5;
   c->tune.small.mac_mode = LRHE_MAC_MODE_HALF;
+  c->tune.small.le_mac_p = 5;
   // moduli and twiddle tables (data primes, P, t)
   std::vector<uint32_t> all = qs;
   all.push_back(p->t);
@@ -1242,6 +1246,7 @@ static int* knob_field(lrhe::Knobs* kn, const std::string& k) {
   if (k == "le_moddown") return &kn->le_moddown;
   if (k == "le_mask") return &kn->le_mask;
   if (k == "mac_mode") return &kn->mac_mode;
+  if (k == "le_mac_p") return &kn->le_mac_p;
   if (k == "fuse_intt") return &kn->fuse_intt;
   return nullptr;
 }
@@ -1289,7 +1294,7 @@ extern "C" int lrhe_tune_get(const lrhe_ctx* c, const char* key, int* value) {
 // ------------------------------------------------------------------ tuning cache
 // One line per key: "<key>\t<name>=<value> <name>=<value> ..." with the names of
 // lrhe_tune_get (both classes, tile, small_below).
-static const char* const k_tune_names[] = {"le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt"};
+static const char* const k_tune_names[] = {"le_intt", "le_mac", "le_moddown", "le_mask", "mac_mode", "fuse_intt", "le_mac_p"};
 
 extern "C" int lrhe_tune_save(const lrhe_ctx* c, const char* path, const char* key) {
   if (!c || !path || !key) return fail(LRHE_EINVAL, "null argument");
@@ -1362,7 +1367,7 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   // the class of this job's tiles is the one tuned
   const uint64_t npairs = (uint64_t)rows * m->classes;
   lrhe::Knobs& K = c->tune.knobs(std::min<uint64_t>(npairs, c->tune.tile));
-  const char* names[5] = {"k_ks_intt", "k_ks_moddown", "k_mask", "k_ks_mac", "k_ks_rho"};
+  const char* names[7] = {"k_ks_intt", "k_ks_moddown", "k_mask", "k_ks_mac", "k_ks_rho", "k_ks_mac_p", "k_ks_mac_md"};
   int* knobs[3] = {&K.le_intt, &K.le_moddown, &K.le_mask};
   double best_ms[3] = {1e300, 1e300, 1e300};
   int best_le[3] = {K.le_intt, K.le_moddown, K.le_mask};
@@ -1371,6 +1376,9 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   // k_ks_moddown), which the others are compared against with their best k_ks_moddown
   const bool small_class = &K == &c->tune.small;
   double mac_ms[3][LRHE_MAC_NMODES], half_ms[3];
+  // the split variant's special-prime launch keeps its own fastest residues per thread
+  double best_p_ms = 1e300;
+  int best_p_le = K.le_mac_p;
   for (auto& row : mac_ms)
     for (double& v : row) v = 1e300;
   for (double& v : half_ms) v = 1e300;
@@ -1397,12 +1405,12 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   // residues per thread and variant
   for (int le = 4; le <= 6; ++le) {
     if (!le_valid(c->logn, le)) continue;
-    K.le_intt = K.le_moddown = K.le_mask = K.le_mac = le;
+    K.le_intt = K.le_moddown = K.le_mask = K.le_mac = K.le_mac_p = le;
     for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
       if (mode == LRHE_MAC_MODE_HALF && !small_class) continue;
       K.mac_mode = mode;
-      double ms[5];
-      const int rc = timed(ms, 5);
+      double ms[7];
+      const int rc = timed(ms, 7);
       if (rc != LRHE_OK) return rc;
       if (mode == 0) {
         for (int k = 0; k < 3; ++k)
@@ -1411,7 +1419,13 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
             best_le[k] = le;
           }
       }
-      mac_ms[le - 4][mode] = ms[3];
+      // the split variant: its data-modulus launch, which includes part 3 (no
+      // k_ks_moddown); its special-prime launch is chosen on its own
+      mac_ms[le - 4][mode] = mode == LRHE_MAC_MODE_SPLIT ? ms[6] : ms[3];
+      if (mode == LRHE_MAC_MODE_SPLIT && ms[5] < best_p_ms) {
+        best_p_ms = ms[5];
+        best_p_le = le;
+      }
       // the digit-halves variant runs k_ks_intt on every step (the others on
       // the first only, when k_ks_moddown writes the next step's digits)
       if (mode == LRHE_MAC_MODE_HALF) half_ms[le - 4] = ms[3] + ms[4] + ms[1] + ms[0];
@@ -1422,8 +1436,9 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   int best_mac_le = K.le_mac, best_mode = 0;
   for (int le = 4; le <= 6; ++le)
     for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
-      const double cost =
-          mode == LRHE_MAC_MODE_HALF ? half_ms[le - 4] : mac_ms[le - 4][mode] + best_ms[1] + best_ms[0];
+      const double cost = mode == LRHE_MAC_MODE_HALF    ? half_ms[le - 4]
+                          : mode == LRHE_MAC_MODE_SPLIT ? mac_ms[le - 4][mode] + best_p_ms + best_ms[0]
+                                                        : mac_ms[le - 4][mode] + best_ms[1] + best_ms[0];
       if (cost < best) {
         best = cost;
         best_mac_le = le;
@@ -1435,5 +1450,6 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   if (best_mode == LRHE_MAC_MODE_HALF) K.le_moddown = best_mac_le;
   K.le_mac = best_mac_le;
   K.mac_mode = best_mode;
+  K.le_mac_p = best_p_le;
   return LRHE_OK;
 }

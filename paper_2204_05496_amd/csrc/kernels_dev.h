@@ -514,6 +514,44 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
   store0<G>(DBuf(D + (lp * c.L + i) * G::N, G::N), x, t);
 }
 
+// Part 3 of the key switch for one limb r and one ciphertext part (PART 0 =
+// b, 1 = a) from the part's inner-product sum acc (registers, last-pass layout,
+// [0, 2 q_r)): out = (acc - NTT_r(rho_PART - h)) P^-1 mod q_r, then the
+// rotate-and-accumulate, c0 + sigma_g(c0) + out for b, c1 + out for a, stored
+// to dst.  The same arithmetic as k_ks_moddown.  A template on the part, so
+// that acc is always a register array under constant indices.
+template <class G, bool DB, bool PF, int PART>
+__device__ __forceinline__ void ks_part3_limb(const uint32_t* acc, uint32_t* x, uint32_t* lds, int* par,
+                                              const TwView& tw, const Mod& mr, uint32_t hq, uint32_t pinv,
+                                              const DBuf& rho, const DBuf& c0, const DBuf& cp, uint32_t g,
+                                              const DBuf& dst) {
+  __builtin_amdgcn_sched_barrier(0);
+  {
+    const uint32_t t0 = (uint32_t)tid_fresh();
+    // rho - h + q_r < P + q_r < 4 q_r is a valid lazy input
+#pragma unroll
+    for (int e = 0; e < G::E; ++e) x[e] = rho.at(t0, (uint32_t)PART * G::N + G::eoff(0, e)) + mr.q - hq;
+  }
+  ntt_fwd<G, DB, PF>(x, lds, tw, mr, tid_fresh(), par);
+  __builtin_amdgcn_sched_barrier(0);
+  const int t1 = tid_fresh();
+  const uint32_t bL = G::tbase(G::NPASS - 1, t1);
+#pragma unroll
+  for (int e = 0; e < G::E; e += 4) {
+    const u32x4 v = ld4L<G>(cp, bL, 0, e);
+    const uint32_t cv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int ee = e + k4;
+      const uint32_t o = red1(mulm(red1(acc[ee], mr.q) + mr.q - x[ee], pinv, mr.q, mr.qinv), mr.q);
+      uint32_t v2 = cv[k4];
+      if constexpr (PART == 0) v2 = addm(v2, c0[auto_perm(bL + G::eoff(G::NPASS - 1, ee), g, G::LOGN)], mr.q);
+      x[ee] = addm(v2, o, mr.q);
+    }
+  }
+  storeL<G>(dst, x, t1);
+}
+
 // key switch, part 2: for target modulus r, acc_x = sum_i NTT_r(d_i) ksk_{g,i,x,r}
 // (for i = r the transform is skipped: NTT_r(d_r) is limb r of sigma_g(c1));
 // r = P additionally returns rho_x = [INTT(acc_x) + (P-1)/2]_P in coefficient form
@@ -527,12 +565,18 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // every 4 digits) instead of reducing every product; 256 = two workgroups per
 // item, one for each half of the digits, writing their sums to ACC and ACC2
 // (canonical, no inverse transform for r = P; k_ks_rho finishes that item);
-// 512 = target moduli by XCD (below).
+// 512 = target moduli by XCD (below).  1024 and 2048 split a step's items
+// over two launches: 1024 runs the special-prime items only (one workgroup per
+// pair, rho to ACC as above); 2048 then runs the L data-modulus items, and each
+// finishes part 3 for its own limb r from the sums in its registers: the
+// rounded division by P (rho from ACC, transformed mod q_r) and the
+// rotate-and-accumulate, written to cout, so no sum goes through ACC and no
+// k_ks_moddown launch follows.  The arithmetic is that of k_ks_moddown.
 template <int LOGN, int LE, int MODE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
     DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
     const uint32_t* __restrict__ gk_default, uint32_t gi, uint32_t g, uint32_t* __restrict__ ACC,
-    uint32_t* __restrict__ ACC2) {
+    uint32_t* __restrict__ ACC2, uint32_t* __restrict__ cout) {
   constexpr bool DB = (MODE & 1) && 2 * Geom<LOGN, LE>::LDS_WORDS * 4 <= 160 * 1024;
   // the wave-local last-pass blocks only pay where they remove barriers
   // (single buffer); double-buffered, the plain numbering measured faster
@@ -578,6 +622,19 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
       lp = p0 + (x / 4) * (wl / 2) + k / 2;
       r = (int)(2 * ((x + w) % 4) + (k & 1));
     }
+  }
+  constexpr bool PONLY = (MODE & 1024) != 0, MD = (MODE & 2048) != 0;
+  static_assert(!((PONLY || MD) && (MODE & (32 | 64 | 256 | 512))), "the split launches have their own item maps");
+  if constexpr (PONLY) {
+    lp = blockIdx.x;
+    r = L;
+  }
+  if constexpr (MD) {
+    // L workgroups per pair, the pair's workgroups on one XCD (as MODE 64)
+    uint32_t lj = blockIdx.x;
+    if (gridDim.x % 8 == 0) lj = (lj % 8) * (gridDim.x / 8) + lj / 8;
+    lp = lj / L;
+    r = (int)(lj % L);
   }
   // digits of this workgroup: all of them, or one half
   const int half = HALF ? wi & 1 : 0;
@@ -682,6 +739,19 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
       ab[e] = red2(redc(fold32(ab64[e], r1), mr.q, mr.qinv), mr.q);
       aa[e] = red2(redc(fold32(aa64[e], r1), mr.q, mr.qinv), mr.q);
     }
+  }
+  if constexpr (MD) {
+    // part 3 for limb r: out_x = (acc_x - NTT_r(rho_x - h)) P^-1 mod q_r, then
+    // c0' = c0 + sigma_g(c0) + out_b and c1' = c1 + out_a
+    const DBuf rho(ACC + (lp * (L + 1) + L) * 2 * G::N, 2 * G::N);
+    const DBuf c0(cin + (lp * 2 * L + r) * G::N, G::N);
+    const DBuf c1(cin + (lp * 2 * L + L + r) * G::N, G::N);
+    uint32_t* co = cout + lp * 2 * L * G::N;
+    ks_part3_limb<G, DB, PF, 0>(ab, x, lds, &par, tw, mr, c.hmod[r], c.pinv_m[r], rho, c0, c0, g,
+                                DBuf(co + (size_t)r * G::N, G::N));
+    ks_part3_limb<G, DB, PF, 1>(aa, x, lds, &par, tw, mr, c.hmod[r], c.pinv_m[r], rho, c0, c1, g,
+                                DBuf(co + (size_t)(L + r) * G::N, G::N));
+    return;
   }
   const int t = tid_fresh();
   uint32_t* out = (half ? ACC2 : ACC) + (lp * (L + 1) + r) * 2 * G::N;

@@ -26,7 +26,7 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
 // k_ks_mac variants selectable through the "mac_mode" tuning key (index -> MODE bits)
 #ifndef LRHE_MAC_MODES
 #define LRHE_MAC_MODE_CASE(IDX, LN, LE, MODE) \
-  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC, ACC2); break;
+  case IDX: k_ks_mac<LN, LE, MODE><<<grid, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC, ACC2, nxt); break;
 #define LRHE_MAC_MODES(LN, LE)                                                           \
   LRHE_MAC_MODE_CASE(0, LN, LE, 104) /* one buffer, 2 workgroups/CU, pair per XCD, rotated */ \
   LRHE_MAC_MODE_CASE(1, LN, LE, 108) /* as 0, with twiddle prefetch */                       \
@@ -34,6 +34,8 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
   LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */                           \
   LRHE_MAC_MODE_CASE(4, LN, LE, 385) /* double buffer, 64-bit MAC, two workgroups per item (digit halves) */ \
   LRHE_MAC_MODE_CASE(5, LN, LE, 524) /* one buffer, 2 workgroups/CU, twiddle prefetch, moduli by XCD */
+/* mac_mode 6 (LRHE_MAC_MODE_SPLIT) is launched on its own below: MODE 1036 = the
+   special-prime items, then MODE 2060 = the data-modulus items with part 3 */
 #endif
 
 template <int LN>
@@ -56,6 +58,25 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
     LRHE_LE_SWITCH(kn.le_intt, {
       k_ks_intt<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, g, D);
     });
+  }
+  if (kn.mac_mode == LRHE_MAC_MODE_SPLIT) {
+    // the special-prime items (rho to ACC), then the L data-modulus items, each
+    // ending with the rounded division by P and the rotate-and-accumulate of
+    // its limb (the next step's digits come from k_ks_intt)
+    if (d_next) return hipErrorInvalidValue;
+    {
+      ProfScope ps(s, "k_ks_mac_p");
+      LRHE_LE_SWITCH(kn.le_mac_p, {
+        k_ks_mac<LN, LE, 1036><<<(unsigned)Bt, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC, nullptr,
+                                                                       nxt);
+      });
+    }
+    ProfScope ps(s, "k_ks_mac_md");
+    LRHE_LE_SWITCH(kn.le_mac, {
+      k_ks_mac<LN, LE, 2060><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC,
+                                                                           nullptr, nxt);
+    });
+    return hipGetLastError();
   }
   {
     ProfScope ps(s, "k_ks_mac");

@@ -74,16 +74,20 @@ namespace lrhe {
 // Launch choices of the fast-matmul kernels (set by lrhe_tune_set / lrhe_autotune_fast):
 // log2 of the residues per thread of each transform kernel, pairs per tile.
 #ifndef LRHE_MAC_NMODES
-#define LRHE_MAC_NMODES 6   // k_ks_mac variants behind the "mac_mode" tuning key
+#define LRHE_MAC_NMODES 7   // k_ks_mac variants behind the "mac_mode" tuning key
 #endif
 // the variant that splits each key-switch item's digits over two workgroups
 // (latency of small tiles); it needs two accumulator slots per tile pair, so
 // it is a choice of the small-tile class only
 #define LRHE_MAC_MODE_HALF 4
+#define LRHE_MAC_MODE_SPLIT 6   // special-prime items, then data-modulus items with part 3
 // Launch choices of the transform kernels (none changes a result bit).
 struct Knobs {
   int le_intt = 5, le_mac = 5, le_moddown = 5, le_mask = 5;
   int mac_mode = 0;   // variant of k_ks_mac, 0 .. LRHE_MAC_NMODES - 1
+  // residues per thread of the special-prime launch of the split variant
+  // (le_mac sets its data-modulus launch)
+  int le_mac_p = 5;
   // k_ks_moddown also writes the next step's digits (no k_ks_intt after the
   // first step); not with the digit-halves variant, whose division by P is
   // split.  Off by default: at 512 x 40,000 the extra inverse transform costs
@@ -94,7 +98,7 @@ struct Knobs {
 // holds) and larger tiles (throughput-bound) keep separate choices.
 struct Tune {
   Knobs large;
-  Knobs small{5, 5, 5, 5, 3};
+  Knobs small{5, 5, 5, 5, 3, 5};
   uint32_t tile = 4096;
   uint32_t small_below = 64;
   const Knobs& knobs(uint64_t tile_pairs) const { return tile_pairs < small_below ? small : large; }
