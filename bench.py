@@ -593,7 +593,6 @@ def main():
     ws_enc = ctx.workspace(P.native.WS_ENCRYPT_ROWS, rows, wl.f)
     nout = -(-rows * classes // ctx.n)
     y = ctx.empty_ct(nout)
-    ws = ctx.workspace(P.native.WS_MATMUL_FAST, rows, wl.f, classes)
     plain = O.plain_scores(wl.X, wl.W, wl.b, p.t)
     # pick residues-per-thread of the transform kernels by timing them on this workload
     ctx.encrypt_rows(keys, Xd, seed=3, out=xct, ws=ws_enc)
@@ -604,6 +603,9 @@ def main():
     # launch choices: as given, from the tuning cache, or autotuned (both tile
     # classes: this job's tiles here, the single inference's below) and cached
     cached = not fixed and tune_from_cache(ctx, torch, args)
+    # the workspace depends on the tile size, one of the choices just set (the
+    # autotuner below keeps the tile)
+    ws = ctx.workspace(P.native.WS_MATMUL_FAST, rows, wl.f, classes)
     tuning_source = "fixed" if fixed else ("cache" if cached else "autotuned")
     tuned = ctx.tuning() if fixed or cached else ctx.autotune_fast(keys, model, xct, rows, out=y, ws=ws)
     if not fixed and not cached and args.no_extras:
@@ -655,7 +657,7 @@ def main():
     log("step ms", ms_step, "kernels", json.dumps(kern))
 
     # roofline of the dominant kernel (key-switch digit transforms + inner product)
-    lay_B = min(4096, rows * classes)
+    lay_B = min(int(tuned["tile"]), rows * classes)   # pairs per launch
     # the split variant's dominant kernel is its data-modulus launch
     split = tuned["large"]["mac_mode"] == P.native.MAC_MODE_SPLIT
     mac_name = "k_ks_mac_md" if split else "k_ks_mac"
@@ -665,7 +667,9 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": mac_name, "achieved": round(achieved, 3), "peak": round(MODMUL_PEAK_T, 3),
                 "unit": "Tmodmul/s", "frac": round(achieved / MODMUL_PEAK_T, 4),
-                "traffic": counted_traffic(tuned["large"]["le_mac"], tuned["large"]["mac_mode"]) if rows * classes >= 4096 else None,
+                # the counter summaries are per launch of 4096 pairs
+                "traffic": (counted_traffic(tuned["large"]["le_mac"], tuned["large"]["mac_mode"])
+                            if lay_B == 4096 else None),
                 "avg_launch_ms": round(avg_ms, 4), "modmul_per_launch": per_launch}
 
     # server-only rate (Algorithm 1 on resident ciphertexts)

@@ -91,6 +91,8 @@ def test_every_tuning_choice_same_bits(P, torch, pname, rows, f, classes):
     for le, mode, fuse in itertools.product(les, range(P.native.MAC_MODES), (0, 1)):
         for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
             ctx.tune_set(knob, le)
+        # the split variant's special-prime launch: a different choice from le_mac
+        ctx.tune_set("le_mac_p", les[(les.index(le) + 1) % len(les)])
         ctx.tune_set("small.mac_mode", mode)   # every tile of these jobs is in the small class
         ctx.tune_set("fuse_intt", fuse)
         say(pname, "le", le, "mac_mode", mode, "fuse_intt", fuse)
@@ -120,7 +122,8 @@ def test_autotuner_keeps_bits(P, torch):
     say("autotuned", tuned)
     for cls in ("small", "large"):
         t = tuned[cls]
-        assert t["mac_mode"] in range(P.native.MAC_MODES) and all(t[k] in (4, 5, 6) for k in ("le_intt", "le_mac", "le_moddown"))
+        assert t["mac_mode"] in range(P.native.MAC_MODES) and all(t[k] in (4, 5, 6)
+                                                                  for k in ("le_intt", "le_mac", "le_moddown", "le_mac_p"))
     assert tuned["large"]["mac_mode"] != P.native.MAC_MODE_HALF
     y = ctx.matmul_fast(keys, model, xct, wl.rows)
     torch.cuda.synchronize()

@@ -188,6 +188,7 @@ def test_tuning_cache_round_trip(P, tmp_path):
     assert not a.tune_load(path, "gfx950/n16384/L7/x")            # no file yet
     a.tune_set("large.le_mac", 5)
     a.tune_set("large.mac_mode", 2)
+    a.tune_set("large.le_mac_p", 4)
     a.tune_set("small.le_intt", 6)
     a.tune_set("tile", 2048)
     a.tune_save(path, "gfx950/n16384/L7/x")
