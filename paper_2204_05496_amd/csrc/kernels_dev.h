@@ -572,9 +572,14 @@ __device__ __forceinline__ void ks_part3_limb(const uint32_t* acc, uint32_t* x, 
 // rounded division by P (rho from ACC, transformed mod q_r) and the
 // rotate-and-accumulate, written to cout, so no sum goes through ACC and no
 // k_ks_moddown launch follows.  The arithmetic is that of k_ks_moddown.
+// 4096 (with 1024): the special-prime workgroup of a pair also makes the
+// pair's digits, k_ks_intt's steps for each limb i (sigma_g of limb i of c1
+// through LDS, inverse transform mod q_i), stores them to D for the
+// data-modulus launch and transforms the same registers mod P; no k_ks_intt
+// launch precedes.
 template <int LOGN, int LE, int MODE>
 __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::T / 128 : 1)) void k_ks_mac(
-    DevCtx c, const uint32_t* __restrict__ cin, const uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
+    DevCtx c, const uint32_t* __restrict__ cin, uint32_t* __restrict__ D, const PairDesc* __restrict__ pairs,
     const uint32_t* __restrict__ gk_default, uint32_t gi, uint32_t g, uint32_t* __restrict__ ACC,
     uint32_t* __restrict__ ACC2, uint32_t* __restrict__ cout) {
   constexpr bool DB = (MODE & 1) && 2 * Geom<LOGN, LE>::LDS_WORDS * 4 <= 160 * 1024;
@@ -623,7 +628,8 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
       r = (int)(2 * ((x + w) % 4) + (k & 1));
     }
   }
-  constexpr bool PONLY = (MODE & 1024) != 0, MD = (MODE & 2048) != 0;
+  constexpr bool PONLY = (MODE & 1024) != 0, MD = (MODE & 2048) != 0, DIG = (MODE & 4096) != 0;
+  static_assert(!DIG || (PONLY && !DP && !DB), "digits are made by the single-buffered special-prime launch");
   static_assert(!((PONLY || MD) && (MODE & (32 | 64 | 256 | 512))), "the split launches have their own item maps");
   if constexpr (PONLY) {
     lp = blockIdx.x;
@@ -675,7 +681,28 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
       for (int e = 0; e < G::E; ++e) x[e] = c1r[auto_perm(idxLf<G>(e), g, LOGN)];
     } else {
       // d_i < q_i < 4 q_r: a valid lazy input
-      if constexpr (DP) {
+      if constexpr (DIG) {
+        // d_i = INTT_i(sigma_g(limb i of c1)), as k_ks_intt: the limb to LDS at its
+        // natural positions (after every wave has read the last exchange), the
+        // permutation gathered into the last-pass layout, the inverse transform
+        const DBuf src(cin + (lp * 2 * L + L + i) * G::N, G::N);
+        __syncthreads();
+        {
+          const int tt = tid_fresh();
+          uint32_t* wr = lds + G::pad((uint32_t)tt);
+#pragma unroll
+          for (int e = 0; e < G::E; ++e) wr[G::padoff(G::eoff(0, e))] = src.at((uint32_t)tt, G::eoff(0, e));
+        }
+        __syncthreads();
+        {
+          const int tt = tid_fresh();
+#pragma unroll
+          for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(idxL<G>(e, tt), g, LOGN))];
+        }
+        ntt_inv<G>(x, lds, twv(c.itw, i, G::N), c.mod[i], tid_fresh());
+        store0<G>(DBuf(D + (lp * L + i) * G::N, G::N), x, tid_fresh());
+        __builtin_amdgcn_sched_barrier(0);
+      } else if constexpr (DP) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) x[e] = xn[e];
         int nx = i + 1;

@@ -34,8 +34,8 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
   LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */                           \
   LRHE_MAC_MODE_CASE(4, LN, LE, 385) /* double buffer, 64-bit MAC, two workgroups per item (digit halves) */ \
   LRHE_MAC_MODE_CASE(5, LN, LE, 524) /* one buffer, 2 workgroups/CU, twiddle prefetch, moduli by XCD */
-/* mac_mode 6 (LRHE_MAC_MODE_SPLIT) is launched on its own below: MODE 1036 = the
-   special-prime items, then MODE 2060 = the data-modulus items with part 3 */
+/* mac_mode 6 (LRHE_MAC_MODE_SPLIT) is launched on its own below: MODE 5132 = the
+   special-prime items with the digits, then MODE 2060 = the data-modulus items with part 3 */
 #endif
 
 template <int LN>
@@ -52,22 +52,24 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
     ACC2 = ACC + (uint64_t)Bt * (L + 1) * 2 * c->n;
   }
   // the digits of this step: from k_ks_intt, or already written by the
-  // previous step's k_ks_moddown (d_ready)
-  if (!d_ready) {
+  // previous step's k_ks_moddown (d_ready), or (split variant) made by its
+  // special-prime launch
+  const bool split = kn.mac_mode == LRHE_MAC_MODE_SPLIT;
+  if (!d_ready && !split) {
     ProfScope ps(s, "k_ks_intt");
     LRHE_LE_SWITCH(kn.le_intt, {
       k_ks_intt<LN, LE><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, g, D);
     });
   }
-  if (kn.mac_mode == LRHE_MAC_MODE_SPLIT) {
-    // the special-prime items (rho to ACC), then the L data-modulus items, each
-    // ending with the rounded division by P and the rotate-and-accumulate of
-    // its limb (the next step's digits come from k_ks_intt)
-    if (d_next) return hipErrorInvalidValue;
+  if (split) {
+    // the special-prime items, which also make the step's digits (D) and rho
+    // (ACC), then the L data-modulus items, each ending with the rounded
+    // division by P and the rotate-and-accumulate of its limb
+    if (d_next || d_ready) return hipErrorInvalidValue;
     {
       ProfScope ps(s, "k_ks_mac_p");
       LRHE_LE_SWITCH(kn.le_mac_p, {
-        k_ks_mac<LN, LE, 1036><<<(unsigned)Bt, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC, nullptr,
+        k_ks_mac<LN, LE, 5132><<<(unsigned)Bt, Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC, nullptr,
                                                                        nxt);
       });
     }
