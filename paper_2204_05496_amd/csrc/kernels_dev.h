@@ -518,8 +518,11 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
 // b, 1 = a) from the part's inner-product sum acc (registers, last-pass layout,
 // [0, 2 q_r)): out = (acc - NTT_r(rho_PART - h)) P^-1 mod q_r, then the
 // rotate-and-accumulate, c0 + sigma_g(c0) + out for b, c1 + out for a, stored
-// to dst.  The same arithmetic as k_ks_moddown.  A template on the part, so
-// that acc is always a register array under constant indices.
+// to dst.  The values of k_ks_moddown: out is the canonical residue of a
+// product, so it does not depend on which representatives enter it; here acc
+// stays in [0, 2q) and the transform's output is only brought to [0, 2q), and
+// acc + 2q - x < 4q.  A template on the part, so that acc is always a register
+// array under constant indices.
 template <class G, bool DB, bool PF, int PART>
 __device__ __forceinline__ void ks_part3_limb(const uint32_t* acc, uint32_t* x, uint32_t* lds, int* par,
                                               const TwView& tw, const Mod& mr, uint32_t hq, uint32_t pinv,
@@ -532,10 +535,11 @@ __device__ __forceinline__ void ks_part3_limb(const uint32_t* acc, uint32_t* x, 
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = rho.at(t0, (uint32_t)PART * G::N + G::eoff(0, e)) + mr.q - hq;
   }
-  ntt_fwd<G, DB, PF>(x, lds, tw, mr, tid_fresh(), par);
+  ntt_fwd<G, DB, PF, TwView, true>(x, lds, tw, mr, tid_fresh(), par);   // [0, 4q)
   __builtin_amdgcn_sched_barrier(0);
   const int t1 = tid_fresh();
   const uint32_t bL = G::tbase(G::NPASS - 1, t1);
+  const uint32_t q2 = 2 * mr.q;
 #pragma unroll
   for (int e = 0; e < G::E; e += 4) {
     const u32x4 v = ld4L<G>(cp, bL, 0, e);
@@ -543,7 +547,7 @@ __device__ __forceinline__ void ks_part3_limb(const uint32_t* acc, uint32_t* x, 
 #pragma unroll
     for (int k4 = 0; k4 < 4; ++k4) {
       const int ee = e + k4;
-      const uint32_t o = red1(mulm(red1(acc[ee], mr.q) + mr.q - x[ee], pinv, mr.q, mr.qinv), mr.q);
+      const uint32_t o = red1(mulm(acc[ee] + q2 - umin(x[ee], x[ee] - q2), pinv, mr.q, mr.qinv), mr.q);
       uint32_t v2 = cv[k4];
       if constexpr (PART == 0) v2 = addm(v2, c0[auto_perm(bL + G::eoff(G::NPASS - 1, ee), g, G::LOGN)], mr.q);
       x[ee] = addm(v2, o, mr.q);

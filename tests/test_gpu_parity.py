@@ -211,16 +211,17 @@ def test_single_40k_standard(n16k, torch):
     assert np.array_equal(n16k.coeff(ctx.matmul_standard(ms, fct)), o.standard_matmul(fo, Ws, wl.b))
 
 
-@pytest.mark.parametrize("cls", ["small", "large", "large_xcd", "large_split"])
+@pytest.mark.parametrize("cls", ["small", "large", "large_xcd", "large_plain"])
 @pytest.mark.parametrize("stage", [1, 2 + 1, 2 + 7, 2 + 14, 100, 0])
 def test_stage_parity_n16k(n16k, torch, P, stage, cls):
     """Per-pair ciphertext after each stage at n = 16384, L = 7 (1 x 40,000 x 16):
     chunk products (1), 1, 7 and all 14 rotate-and-accumulate steps, bias (100)
     and mask (0), with the small-tile kernels (digit halves), with the
-    large-tile ones (the same 16 pairs run as a large tile), with the
-    large-tile inner-product variant that spreads the target moduli by XCD and
-    with the split variant (special-prime items first, then the data-modulus
-    items ending with the division by P); three pairs each against the oracle."""
+    large-tile ones (the same 16 pairs run as a large tile: by default the split
+    launches, special-prime items with the digits first, then the data-modulus
+    items ending with the division by P), with the large-tile variant that
+    spreads the target moduli by XCD and with the plain one (k_ks_intt,
+    k_ks_mac, k_ks_moddown); three pairs each against the oracle."""
     wl = WL.single()
     ctx, o = n16k.ctx, n16k.o
     say("stage", stage, cls)
@@ -230,8 +231,8 @@ def test_stage_parity_n16k(n16k, torch, P, stage, cls):
         ctx.tune_set("small_below", 1)
     if cls == "large_xcd":
         ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD)
-    if cls == "large_split":
-        ctx.tune_set("large.mac_mode", P.native.MAC_MODE_SPLIT)
+    if cls == "large_plain":
+        ctx.tune_set("large.mac_mode", 1)
     try:
         xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=17)
         model = ctx.model(wl.W, wl.b)
@@ -292,18 +293,18 @@ def test_batch_512x40k_launch_config(n16k, torch):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", ["xcd", "split"])
+@pytest.mark.parametrize("variant", ["xcd", "plain"])
 def test_batch_512x40k_variants(n16k, torch, P, variant):
-    """The throughput workload with the other large-tile key-switch variants:
+    """The throughput workload with the other large-tile key-switch variants
+    (the default, the split launches, is the launch configuration test's):
     target moduli spread by XCD per window of pairs (its own workgroup-to-item
-    map), and the split launches (special-prime items, then data-modulus items
-    that finish the division by P from their registers).  The whole output
-    ciphertext equals the oracle's stored one."""
+    map), and the plain sequence k_ks_intt, k_ks_mac, k_ks_moddown.  The whole
+    output ciphertext equals the oracle's stored one."""
     import golden_ref
     wl = WL.batch()
     ctx = n16k.ctx
     keep = ctx.tune_get("large.mac_mode")
-    ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD if variant == "xcd" else P.native.MAC_MODE_SPLIT)
+    ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD if variant == "xcd" else 1)
     try:
         say("batch encrypt")
         xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=3)
