@@ -338,7 +338,8 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * pairs, so its L2 holds a quarter of the step's Galois key (needs L = 7 and
  * an even tile; otherwise the plain launch order); 6: two launches per
  * rotation step, the special-prime items first (at "le_mac_p" residues per
- * thread), then the data-modulus items, each of which also does the rounded
+ * thread; they also make the step's digits, so no digit kernel runs), then the
+ * data-modulus items, each of which also does the rounded
  * division by P and the rotate-and-accumulate of its limb from the sums in its
  * registers, so no k_ks_moddown runs and no sum of a data modulus goes through
  * memory; "le_mac_p" = residues per thread of that special-prime launch;
