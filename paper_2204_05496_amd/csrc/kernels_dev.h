@@ -167,10 +167,12 @@ __device__ __forceinline__ void ntt_inv(uint32_t* x, uint32_t* lds, const TW& it
 #pragma unroll
   for (int p = G::NPASS - 1; p >= 0; --p) {
     if (p < G::NPASS - 1) xchg<G, DB>(lds, p + 1, p, x, t, par);
-    inv_pass<G, PF, STRICT>(p, t, x, itw, m.q, m.qinv);
+    // pass 0 ends with the transform's last stage, which also scales by n^-1
+    if (p == 0) inv_pass<G, PF, STRICT, TW, true>(p, t, x, itw, m.q, m.qinv, m.ninv_m);
+    else inv_pass<G, PF, STRICT>(p, t, x, itw, m.q, m.qinv);
   }
 #pragma unroll
-  for (int e = 0; e < G::E; ++e) x[e] = red1(mulm(x[e], m.ninv_m, m.q, m.qinv), m.q);
+  for (int e = 0; e < G::E; ++e) x[e] = red1(x[e], m.q);
 }
 
 // pass-0 layout: element e of thread t is index e T + t (coalesced).  Offsets

@@ -213,8 +213,11 @@ LRHE_HD void fwd_pass(int p, int t, uint32_t* x, const TW& tw, uint32_t q, uint3
 // One pass of the inverse (Gentleman-Sande) transform; passes run in the order
 // NPASS-1 .. 0 and stages inside a pass from the last to the first.  Values in
 // and out in [0, 2q).  itw: psi^-brv(k) R mod q.  PF and STRICT as in fwd_pass.
-template <class G, bool PF = false, bool STRICT = false, class TW>
-LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint32_t qinv) {
+// SCALE (pass 0 only): the final stage also multiplies by n^-1 (ninv_m = n^-1 R
+// mod q): its one twiddle w becomes w n^-1, and the sums are scaled, which
+// saves the n^-1 product of the other half of the residues.
+template <class G, bool PF = false, bool STRICT = false, class TW, bool SCALE = false>
+LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint32_t qinv, uint32_t ninv_m = 0) {
   const int rr = G::r(p);
   const int nu = G::E >> rr;
   const uint32_t q2 = 2 * q;
@@ -244,10 +247,20 @@ LRHE_HD void inv_pass(int p, int t, uint32_t* x, const TW& itw, uint32_t q, uint
           U = umin(U, U - q2);
           V = *a + q2 - *b;
         }
-        *a = U;
-        *b = PF ? mulm(V, wc[c >> (rr - tau)], q, qinv)
-                : tw_mul(itw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))), G::s0(p) == 0, V,
-                         q, qinv);
+        if (SCALE && tau == 0) {
+          // the transform's last stage (block index 0, twiddle index 1):
+          // U n^-1 and V w n^-1, w n^-1 canonical so that the products of V < 4q
+          // stay below 2q
+          const uint32_t w = PF ? wc[c >> (rr - tau)] : tw_get(itw, 1u, true);
+          const uint32_t wn = red1(mulm(w, ninv_m, q, qinv), q);
+          *a = mulm(U, ninv_m, q, qinv);
+          *b = mulm(V, wn, q, qinv);
+        } else {
+          *a = U;
+          *b = PF ? mulm(V, wc[c >> (rr - tau)], q, qinv)
+                  : tw_mul(itw, (uint32_t)((1 << (G::s0(p) + tau)) + (h << tau) + (c >> (rr - tau))), G::s0(p) == 0,
+                           V, q, qinv);
+        }
         if constexpr (STRICT) *b = red1(*b, q);
       }
       LRHE_STAGE_FENCE();
