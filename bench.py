@@ -566,8 +566,8 @@ def main():
                          "and write them to PATH as JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
-              "path is a design note, not a build target", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this implementation has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
