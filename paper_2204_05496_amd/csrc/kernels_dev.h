@@ -269,7 +269,8 @@ __device__ __forceinline__ uint64_t fold32(uint64_t x, uint32_t r1) {
 
 // ------------------------------------------------------------------ batched transform
 // One limb per workgroup, at LE_ residues per thread (the forward transform
-// measured fastest at 16, the inverse at 32).
+// measured fastest at 16, the inverse at 32), the next stage's twiddles loaded
+// during the current one.
 template <int LOGN, int LE_, bool INV>
 __global__ __launch_bounds__((Geom<LOGN, LE_>::T)) void k_ntt(DevCtx c, uint32_t* data, uint32_t nmod, uint32_t mod0) {
   using G = Geom<LOGN, LE_>;
@@ -281,11 +282,11 @@ __global__ __launch_bounds__((Geom<LOGN, LE_>::T)) void k_ntt(DevCtx c, uint32_t
   uint32_t x[G::E];
   if (!INV) {
     load0<G>(g, x, t);
-    ntt_fwd<G>(x, lds, twv(c.tw, mi, G::N), c.mod[mi], t);
+    ntt_fwd<G, false, true>(x, lds, twv(c.tw, mi, G::N), c.mod[mi], t);
     storeL<G>(g, x, t);
   } else {
     loadL<G>(g, x, t);
-    ntt_inv<G>(x, lds, twv(c.itw, mi, G::N), c.mod[mi], t);
+    ntt_inv<G, false, true>(x, lds, twv(c.itw, mi, G::N), c.mod[mi], t);
     store0<G>(g, x, t);
   }
 }
