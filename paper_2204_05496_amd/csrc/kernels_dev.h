@@ -399,7 +399,7 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_
   uint32_t U[G::E], x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) U[e] = small_mod(su[idx0<G>(e, t)], md.q);
-  ntt_fwd<G>(U, lds, tw, md, t);
+  ntt_fwd<G, false, true>(U, lds, tw, md, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) {
     const uint32_t k = idx0<G>(e, t);
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_
     const uint32_t delta = addm(red1(mulm(mv[k], c.qdivt_m[j], md.q, md.qinv), md.q), red1(rv[k], md.q), md.q);
     x[e] = addm(small_mod(su[G::N + k], md.q), delta, md.q);
   }
-  ntt_fwd<G>(x, lds, tw, md, t);
+  ntt_fwd<G, false, true>(x, lds, tw, md, t);
   uint32_t* out = ct + ci * 2 * c.L * G::N;
   const DBuf pk0(pk + (size_t)j * G::N, G::N), pk1(pk + (size_t)(c.L + j) * G::N, G::N);
   uint32_t v[G::E];
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_encrypt(DevCtx c, const uint32_
   storeL<G>(DBuf(out + (size_t)j * G::N, G::N), x, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = small_mod(su[2 * G::N + idx0<G>(e, t)], md.q);
-  ntt_fwd<G>(x, lds, tw, md, t);
+  ntt_fwd<G, false, true>(x, lds, tw, md, t);
   loadL<G>(pk1, v, t);
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = addm(red1(mulm(U[e], v[e], md.q, md.qinv), md.q), x[e], md.q);
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(Gm<LOGN>::T) void k_lift_ntt(DevCtx c, const uint32
   uint32_t x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = lift_mont(src[idx0<G>(e, t)], c.t, md);
-  ntt_fwd<G>(x, lds, twv(c.tw, i, G::N), md, t);
+  ntt_fwd<G, false, true>(x, lds, twv(c.tw, i, G::N), md, t);
   storeL<G>(DBuf(out + (pi * c.L + i) * G::N, G::N), x, t);
 }
 
@@ -513,7 +513,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_intt(DevCtx c, const
   uint32_t x[G::E];
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(idxL<G>(e, t), g, LOGN))];
-  ntt_inv<G>(x, lds, twv(c.itw, i, G::N), c.mod[i], t);
+  ntt_inv<G, false, true>(x, lds, twv(c.itw, i, G::N), c.mod[i], t);
   store0<G>(DBuf(D + (lp * c.L + i) * G::N, G::N), x, t);
 }
 
@@ -706,7 +706,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T), ((MODE & 8) ? Geom<LOGN, LE>::
 #pragma unroll
           for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(idxL<G>(e, tt), g, LOGN))];
         }
-        ntt_inv<G>(x, lds, twv(c.itw, i, G::N), c.mod[i], tid_fresh());
+        ntt_inv<G, false, true>(x, lds, twv(c.itw, i, G::N), c.mod[i], tid_fresh());
         store0<G>(DBuf(D + (lp * L + i) * G::N, G::N), x, tid_fresh());
         __builtin_amdgcn_sched_barrier(0);
       } else if constexpr (DP) {
@@ -830,7 +830,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_rho(DevCtx c, uint32
   // below cannot overtake another thread's load.
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] += y[e];
-  ntt_inv<G>(x, lds, twv(c.itw, L, G::N), mp, t);
+  ntt_inv<G, false, true>(x, lds, twv(c.itw, L, G::N), mp, t);
   const uint32_t h = (mp.q - 1) / 2;
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = addm(x[e], h, mp.q);
@@ -859,7 +859,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown_part(DevCtx 
   // rho - h + q_j < P + q_j < 4 q_j is a valid lazy input
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = rho.at((uint32_t)t, G::eoff(0, e)) + md.q - hq;
-  ntt_fwd<G>(x, lds, twv(c.tw, j, G::N), md, t);
+  ntt_fwd<G, false, true>(x, lds, twv(c.tw, j, G::N), md, t);
   uint32_t a[G::E], a2[G::E];
   loadL<G>(DBuf(ACC + slot, G::N), a, t);
   loadL<G>(DBuf(ACC2 + slot, G::N), a2, t);
@@ -912,7 +912,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
   // b part: rho - h + q_j < P + q_j < 4 q_j is a valid lazy input
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = rho.at((uint32_t)t, G::eoff(0, e)) + md.q - hq;
-  ntt_fwd<G>(x, lds, tw, md, t);
+  ntt_fwd<G, false, true>(x, lds, tw, md, t);
   uint32_t a[G::E];
   loadL<G>(acc, a, t);
   uint32_t cz[G::E];
@@ -928,7 +928,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
   // a part
 #pragma unroll
   for (int e = 0; e < G::E; ++e) x[e] = rho.at((uint32_t)t, G::N + G::eoff(0, e)) + md.q - hq;
-  ntt_fwd<G>(x, lds, tw, md, t);
+  ntt_fwd<G, false, true>(x, lds, tw, md, t);
   const DBuf acca(ACC + (lp * (L + 1) + j) * 2 * G::N + G::N, G::N);
   loadL<G>(acca, a, t);
   uint32_t cc[G::E];
@@ -955,7 +955,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_ks_moddown(DevCtx c, co
 #pragma unroll
     for (int e = 0; e < G::E; ++e) x[e] = lds[G::pad(auto_perm(br + G::eoff(G::NPASS - 1, e), gnext, LOGN))];
     const int tf = tid_fresh();
-    ntt_inv<G>(x, lds, twv(c.itw, j, G::N), md, tf);
+    ntt_inv<G, false, true>(x, lds, twv(c.itw, j, G::N), md, tf);
     store0<G>(DBuf(Dn + (lp * L + j) * G::N, G::N), x, tf);
   }
 }
@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__((Geom<LOGN, LE>::T)) void k_mask(DevCtx c, const ui
     const uint32_t el = c.slot_exp[d.slot];
 #pragma unroll
     for (int e = 0; e < Gg::E; ++e) x[e] = lift_mont(mtab[(el * idx0f<Gg>(e)) & twon_mask], c.t, md);
-    ntt_fwd<Gg>(x, lds, tw, md, tid_fresh());
+    ntt_fwd<Gg, false, true>(x, lds, tw, md, tid_fresh());
     __builtin_amdgcn_sched_barrier(0);
     uint32_t w0[Gg::E], w1[Gg::E];
     loadL<Gg>(c0, w0, tid_fresh());
