@@ -100,11 +100,17 @@ KERNEL_SOURCES = ("kernels_dev.h", "ks_step.hip", "kernels.hip", "lrhe_math.h", 
 
 
 def kernel_source_digest():
+    """SHA-256 of the kernel sources with their comments removed: it changes
+    with the code the counters measured, not with its comments."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2204_05496_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2204_05496_amd", "csrc", name), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update(src.encode("utf-8"))
     return h.hexdigest()
 
 
@@ -117,7 +123,7 @@ def counted_traffic(le_mac, mac_mode):
         kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    kv = {k.strip(): (v.split() or [""])[0] for k, v in kv.items()}   # first token: a value may carry a note
     if (kv.get("kernel_source_sha256") != kernel_source_digest() or int(kv.get("le_mac", -1)) != le_mac
             or int(kv.get("mac_mode", -1)) != mac_mode):
         return None

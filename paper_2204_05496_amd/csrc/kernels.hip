@@ -28,7 +28,7 @@ hipError_t launch_ntt(const lrhe_ctx* c, uint32_t* data, uint64_t npolys, uint32
   LRHE_DISPATCH(c->logn, {
     ProfScope ps(s, inverse ? "k_ntt_inv" : "k_ntt_fwd");
     // forward at 16 residues per thread up to n = 16384 (1024 threads), inverse at
-    // 32 (64 for the forward transform was faster on some boxes and slower on
+    // 32 (64 for the forward transform was faster on some MI355X GPUs and slower on
     // others, by about 3 %; the inverse at 64 is several times slower)
     constexpr int LEF = LN <= 14 ? 4 : 5;
     if (inverse) k_ntt<LN, 5, true><<<(unsigned)npolys, Geom<LN, 5>::T, 0, s>>>(c->dc, data, nmod, mod0);
