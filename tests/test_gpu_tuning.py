@@ -99,6 +99,28 @@ def test_every_tuning_choice_same_bits(P, torch, pname, rows, f, classes):
         y = ctx.matmul_fast(keys, model, xct, rows)
         torch.cuda.synchronize()
         assert torch.equal(y, ref), f"le {le} mac_mode {mode} fuse_intt {fuse}"
+    # the large-tile variants on the same job (every tile of it large), among them
+    # the split launches (digits made by the special-prime launch, the division
+    # by P in the data-modulus launch) with L = 1, 2, 3 or 7 data primes
+    keep_sb = ctx.tune_get("small_below")
+    ctx.tune_set("small_below", 1)
+    try:
+        for le, mode in itertools.product(les, range(P.native.MAC_MODES)):
+            if mode == P.native.MAC_MODE_HALF:
+                continue
+            for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
+                ctx.tune_set("large." + knob, le)
+            ctx.tune_set("large.le_mac_p", les[(les.index(le) + 1) % len(les)])
+            ctx.tune_set("large.mac_mode", mode)
+            for fuse in ((0, 1) if mode == 1 else (0,)):
+                ctx.tune_set("large.fuse_intt", fuse)
+                say(pname, "large tiles: le", le, "mac_mode", mode, "fuse_intt", fuse)
+                y = ctx.matmul_fast(keys, model, xct, rows)
+                torch.cuda.synchronize()
+                assert torch.equal(y, ref), f"large tiles: le {le} mac_mode {mode} fuse_intt {fuse}"
+        ctx.tune_set("large.fuse_intt", 0)
+    finally:
+        ctx.tune_set("small_below", keep_sb)
     for knob in ("le_intt", "le_mac", "le_moddown", "le_mask"):
         ctx.tune_set(knob, 5)
     ctx.tune_set("mac_mode", 0)
