@@ -363,7 +363,8 @@ int lrhe_tune_get(const lrhe_ctx* ctx, const char* key, int* value);
 /* Autotuner: runs lrhe_matmul_fast on the given workload (reps timed runs per
  * candidate, each kernel timed with HIP events on its stream) and keeps, in
  * the tuning class of this job's tiles, every transform kernel's fastest
- * residues-per-thread choice, searched jointly with "mac_mode" for k_ks_mac.
+ * residues-per-thread choice, searched jointly with "mac_mode" for k_ks_mac
+ * ("le_mac_p", the split variant's special-prime launch, on its own).
  * Uses the kernel timer (lrhe_prof_*), whose totals it resets. */
 int lrhe_autotune_fast(lrhe_ctx* ctx, const lrhe_gk* gk, const lrhe_model* model, const uint32_t* xct, uint32_t rows,
                        uint32_t* y_out, void* ws, size_t ws_bytes, void* stream, int reps);
