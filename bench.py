@@ -665,7 +665,7 @@ def main():
     # roofline of the dominant kernel (key-switch digit transforms + inner product)
     lay_B = min(int(tuned["tile"]), rows * classes)   # pairs per launch
     # the split variant's dominant kernel is its data-modulus launch
-    split = tuned["large"]["mac_mode"] == P.native.MAC_MODE_SPLIT
+    split = tuned["large"]["mac_mode"] in (P.native.MAC_MODE_SPLIT, P.native.MAC_MODE_SPLIT64)
     mac_name = "k_ks_mac_md" if split else "k_ks_mac"
     c_mac, ms_mac = prof_get(lib, mac_name)
     avg_ms = ms_mac / max(c_mac, 1)

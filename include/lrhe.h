@@ -342,11 +342,13 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
  * data-modulus items, each of which also does the rounded
  * division by P and the rotate-and-accumulate of its limb from the sums in its
  * registers, so no k_ks_moddown runs and no sum of a data modulus goes through
- * memory; "le_mac_p" = residues per thread of that special-prime launch;
+ * memory; 7: as 6 with the data-modulus launch double-buffered and its inner
+ * products summed unreduced in 64 bits (one workgroup per CU); "le_mac_p" =
+ * residues per thread of the special-prime launch of variants 6 and 7;
  * "fuse_intt" = 1 lets the rounded division by P of each
  * rotation step also compute the next step's digits (inverse transform of the
  * automorphism of c1), so the digit kernel runs on the first step only; 0
- * (default) runs it on every step; ignored by variants 4 and 6.  These seven keys exist
+ * (default) runs it on every step; ignored by variants 4, 6 and 7.  These seven keys exist
  * in two classes, for tiles of fewer than
  * "small_below" pairs (default 64; such launches are latency-bound) and for
  * larger tiles: "small.<key>" and "large.<key>" address one class, a bare key

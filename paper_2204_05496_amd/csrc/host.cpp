@@ -1422,8 +1422,9 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
       // the split variant: its data-modulus launch, which includes part 3 (no
       // k_ks_moddown); its special-prime launch, which also makes the digits (no
       // k_ks_intt), is chosen on its own
-      mac_ms[le - 4][mode] = mode == LRHE_MAC_MODE_SPLIT ? ms[6] : ms[3];
-      if (mode == LRHE_MAC_MODE_SPLIT && ms[5] < best_p_ms) {
+      const bool split = mode == LRHE_MAC_MODE_SPLIT || mode == LRHE_MAC_MODE_SPLIT64;
+      mac_ms[le - 4][mode] = split ? ms[6] : ms[3];
+      if (split && ms[5] < best_p_ms) {
         best_p_ms = ms[5];
         best_p_le = le;
       }
@@ -1438,7 +1439,8 @@ extern "C" int lrhe_autotune_fast(lrhe_ctx* c, const lrhe_gk* gk, const lrhe_mod
   for (int le = 4; le <= 6; ++le)
     for (int mode = 0; mode < LRHE_MAC_NMODES; ++mode) {
       const double cost = mode == LRHE_MAC_MODE_HALF    ? half_ms[le - 4]
-                          : mode == LRHE_MAC_MODE_SPLIT ? mac_ms[le - 4][mode] + best_p_ms   // makes its own digits
+                          : (mode == LRHE_MAC_MODE_SPLIT || mode == LRHE_MAC_MODE_SPLIT64)
+                              ? mac_ms[le - 4][mode] + best_p_ms   // makes its own digits
                                                         : mac_ms[le - 4][mode] + best_ms[1] + best_ms[0];
       if (cost < best) {
         best = cost;

@@ -142,7 +142,8 @@ hipError_t launch_plan(const lrhe_ctx* c, const uint32_t* gk_d, const PairDesc* 
     }
     const int steps = (stage >= 2 && stage < 100) ? stage - 2 : (int)c->ngal;
     // digits of step gi + 1 from step gi's division by P where the variant allows
-    const bool fuse = kn.fuse_intt && kn.mac_mode != LRHE_MAC_MODE_HALF && kn.mac_mode != LRHE_MAC_MODE_SPLIT;
+    const bool fuse = kn.fuse_intt && kn.mac_mode != LRHE_MAC_MODE_HALF && kn.mac_mode != LRHE_MAC_MODE_SPLIT &&
+                      kn.mac_mode != LRHE_MAC_MODE_SPLIT64;
     for (int gi = 0; gi < steps; ++gi) {
       hipError_t e = hipErrorInvalidValue;
       const bool d_ready = fuse && gi > 0, d_next = fuse && gi + 1 < steps;

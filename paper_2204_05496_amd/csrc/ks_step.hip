@@ -34,8 +34,10 @@ constexpr bool le_ok = LN - LE <= 10 && !(LE == 4 && LN > 14) && !(LE == 6 && LN
   LRHE_MAC_MODE_CASE(3, LN, LE, 3)   /* double buffer, digit prefetch */                           \
   LRHE_MAC_MODE_CASE(4, LN, LE, 385) /* double buffer, 64-bit MAC, two workgroups per item (digit halves) */ \
   LRHE_MAC_MODE_CASE(5, LN, LE, 524) /* one buffer, 2 workgroups/CU, twiddle prefetch, moduli by XCD */
-/* mac_mode 6 (LRHE_MAC_MODE_SPLIT) is launched on its own below: MODE 5132 = the
-   special-prime items with the digits, then MODE 2060 = the data-modulus items with part 3 */
+/* mac_modes 6 and 7 (LRHE_MAC_MODE_SPLIT, LRHE_MAC_MODE_SPLIT64) are launched on their own
+   below: MODE 5132 = the special-prime items with the digits, then the data-modulus items with
+   part 3: MODE 2060 (one buffer, 2 workgroups/CU) or 2181 (double buffer, unreduced 64-bit
+   inner products) */
 #endif
 
 template <int LN>
@@ -54,7 +56,7 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
   // the digits of this step: from k_ks_intt, or already written by the
   // previous step's k_ks_moddown (d_ready), or (split variant) made by its
   // special-prime launch
-  const bool split = kn.mac_mode == LRHE_MAC_MODE_SPLIT;
+  const bool split = kn.mac_mode == LRHE_MAC_MODE_SPLIT || kn.mac_mode == LRHE_MAC_MODE_SPLIT64;
   if (!d_ready && !split) {
     ProfScope ps(s, "k_ks_intt");
     LRHE_LE_SWITCH(kn.le_intt, {
@@ -75,8 +77,12 @@ hipError_t launch_ks_step(const lrhe_ctx* c, const Knobs& kn, const PairDesc* tp
     }
     ProfScope ps(s, "k_ks_mac_md");
     LRHE_LE_SWITCH(kn.le_mac, {
-      k_ks_mac<LN, LE, 2060><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC,
-                                                                           nullptr, nxt);
+      if (kn.mac_mode == LRHE_MAC_MODE_SPLIT64)
+        k_ks_mac<LN, LE, 2181><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC,
+                                                                             nullptr, nxt);
+      else
+        k_ks_mac<LN, LE, 2060><<<(unsigned)(Bt * L), Geom<LN, LE>::T, 0, s>>>(c->dc, cur, D, tp, gk_d, gi, g, ACC,
+                                                                             nullptr, nxt);
     });
     return hipGetLastError();
   }

@@ -74,13 +74,14 @@ namespace lrhe {
 // Launch choices of the fast-matmul kernels (set by lrhe_tune_set / lrhe_autotune_fast):
 // log2 of the residues per thread of each transform kernel, pairs per tile.
 #ifndef LRHE_MAC_NMODES
-#define LRHE_MAC_NMODES 7   // k_ks_mac variants behind the "mac_mode" tuning key
+#define LRHE_MAC_NMODES 8   // k_ks_mac variants behind the "mac_mode" tuning key
 #endif
 // the variant that splits each key-switch item's digits over two workgroups
 // (latency of small tiles); it needs two accumulator slots per tile pair, so
 // it is a choice of the small-tile class only
 #define LRHE_MAC_MODE_HALF 4
 #define LRHE_MAC_MODE_SPLIT 6   // special-prime items, then data-modulus items with part 3
+#define LRHE_MAC_MODE_SPLIT64 7   // as 6, the data-modulus items double-buffered with 64-bit inner products
 // Launch choices of the transform kernels (none changes a result bit).
 struct Knobs {
   int le_intt = 5, le_mac = 5, le_moddown = 5, le_mask = 5;

@@ -22,10 +22,11 @@ WS_ENCRYPT_ROWS, WS_ENCRYPT_COLS, WS_MATMUL_FAST, WS_MATMUL_STANDARD = 1, 2, 3, 
 CT_HOST = 1   # decryption flag: the ciphertexts are in host memory
 # variants of the key-switch inner-product kernel behind the "mac_mode" tuning key;
 # MAC_MODE_HALF (digit halves on two workgroups per item) is a small-tile choice only
-MAC_MODES = 7
+MAC_MODES = 8
 MAC_MODE_HALF = 4
 MAC_MODE_XCD = 5   # target moduli spread by XCD (L = 7, even tiles)
 MAC_MODE_SPLIT = 6   # special-prime items, then data-modulus items ending with part 3
+MAC_MODE_SPLIT64 = 7   # as MAC_MODE_SPLIT, data-modulus items double-buffered with 64-bit inner products
 
 vp = ctypes.c_void_p
 u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64

@@ -211,7 +211,7 @@ def test_single_40k_standard(n16k, torch):
     assert np.array_equal(n16k.coeff(ctx.matmul_standard(ms, fct)), o.standard_matmul(fo, Ws, wl.b))
 
 
-@pytest.mark.parametrize("cls", ["small", "large", "large_xcd", "large_plain"])
+@pytest.mark.parametrize("cls", ["small", "large", "large_xcd", "large_plain", "large_split64"])
 @pytest.mark.parametrize("stage", [1, 2 + 1, 2 + 7, 2 + 14, 100, 0])
 def test_stage_parity_n16k(n16k, torch, P, stage, cls):
     """Per-pair ciphertext after each stage at n = 16384, L = 7 (1 x 40,000 x 16):
@@ -220,8 +220,9 @@ def test_stage_parity_n16k(n16k, torch, P, stage, cls):
     large-tile ones (the same 16 pairs run as a large tile: by default the split
     launches, special-prime items with the digits first, then the data-modulus
     items ending with the division by P), with the large-tile variant that
-    spreads the target moduli by XCD and with the plain one (k_ks_intt,
-    k_ks_mac, k_ks_moddown); three pairs each against the oracle."""
+    spreads the target moduli by XCD, with the plain one (k_ks_intt,
+    k_ks_mac, k_ks_moddown) and with the split launches whose data-modulus
+    items sum unreduced 64-bit products; three pairs each against the oracle."""
     wl = WL.single()
     ctx, o = n16k.ctx, n16k.o
     say("stage", stage, cls)
@@ -233,6 +234,8 @@ def test_stage_parity_n16k(n16k, torch, P, stage, cls):
         ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD)
     if cls == "large_plain":
         ctx.tune_set("large.mac_mode", 1)
+    if cls == "large_split64":
+        ctx.tune_set("large.mac_mode", P.native.MAC_MODE_SPLIT64)
     try:
         xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=17)
         model = ctx.model(wl.W, wl.b)
@@ -293,18 +296,20 @@ def test_batch_512x40k_launch_config(n16k, torch):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", ["xcd", "plain"])
+@pytest.mark.parametrize("variant", ["xcd", "plain", "split64"])
 def test_batch_512x40k_variants(n16k, torch, P, variant):
     """The throughput workload with the other large-tile key-switch variants
     (the default, the split launches, is the launch configuration test's):
     target moduli spread by XCD per window of pairs (its own workgroup-to-item
-    map), and the plain sequence k_ks_intt, k_ks_mac, k_ks_moddown.  The whole
-    output ciphertext equals the oracle's stored one."""
+    map), the plain sequence k_ks_intt, k_ks_mac, k_ks_moddown, and the split
+    launches with unreduced 64-bit inner products.  The whole output ciphertext
+    equals the oracle's stored one."""
     import golden_ref
     wl = WL.batch()
     ctx = n16k.ctx
     keep = ctx.tune_get("large.mac_mode")
-    ctx.tune_set("large.mac_mode", P.native.MAC_MODE_XCD if variant == "xcd" else 1)
+    ctx.tune_set("large.mac_mode", {"xcd": P.native.MAC_MODE_XCD, "plain": 1,
+                                    "split64": P.native.MAC_MODE_SPLIT64}[variant])
     try:
         say("batch encrypt")
         xct = ctx.encrypt_rows(n16k.keys, wl.X, seed=3)
