@@ -51,10 +51,11 @@ def test_counted_traffic_needs_matching_sources_and_variant(tmp_path, monkeypatc
     assert bench.counted_traffic(6, 6) is None          # sources changed since the counters were taken
 
 
-def test_committed_default_traffic_summary_is_current():
-    """The summary for the default large-tile variant matches the committed kernel
-    sources (the benchmark's roofline traffic field reads it)."""
-    assert bench.counted_traffic(6, 6) is not None
+@pytest.mark.parametrize("le_mac,mac_mode", [(6, 6), (5, 6), (4, 7)])
+def test_committed_traffic_summaries_are_current(le_mac, mac_mode):
+    """The summaries for the large-tile choices the autotuner has picked match the
+    committed kernel sources (the benchmark's roofline traffic field reads them)."""
+    assert bench.counted_traffic(le_mac, mac_mode) is not None
 
 
 def test_more_than_one_gpu_is_refused():
