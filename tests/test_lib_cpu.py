@@ -210,3 +210,25 @@ def test_tuning_cache_round_trip(P, tmp_path):
     with pytest.raises(P.native.LrheError):
         c.tune_load(path, "bad")
     assert c.tuning() == before
+
+
+def test_mac_mode_choices_match_the_library(P):
+    """The binding's variant numbers are the library's: every large-tile variant
+    is accepted except the small-tile-only digit halves, the small class takes
+    the digit halves, and the first number past the last variant is refused."""
+    p = WL.PARAMS["n16k"]
+    c = P.Context.from_params(p, device=-1)
+    nat = P.native
+    for m in range(nat.MAC_MODES):
+        if m == nat.MAC_MODE_HALF:
+            with pytest.raises(nat.LrheError):
+                c.tune_set("large.mac_mode", m)
+        else:
+            c.tune_set("large.mac_mode", m)
+            assert c.tuning()["large"]["mac_mode"] == m
+    c.tune_set("small.mac_mode", nat.MAC_MODE_HALF)
+    assert c.tuning()["small"]["mac_mode"] == nat.MAC_MODE_HALF
+    for bad in (-1, nat.MAC_MODES):
+        with pytest.raises(nat.LrheError):
+            c.tune_set("large.mac_mode", bad)
+    assert nat.MAC_MODE_SPLIT64 == nat.MAC_MODES - 1
