@@ -321,8 +321,8 @@ int lrhe_ntt(lrhe_ctx* ctx, uint32_t* data, uint64_t polys, int inverse, void* s
 
 /* Launch tuning of the fast matmul.  Keys: "le_intt", "le_mac", "le_moddown",
  * "le_mask" = log2 of the residues each thread holds in that transform kernel
- * (4, 5 or 6 where the workgroup stays within 1024 threads; default 5),
- * "mac_mode" = variant of the key-switch inner-product kernel: 0 (default):
+ * (4, 5 or 6 where the workgroup stays within 1024 threads; defaults below),
+ * "mac_mode" = variant of the key-switch inner-product kernel: 0:
  * one LDS exchange buffer and two workgroups per CU, the workgroups of a pair
  * on one XCD; 1: as 0 with the twiddles of the next butterfly stage loaded
  * ahead; 2: double-buffered exchange, pair per XCD, unreduced 64-bit inner
