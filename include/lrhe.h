@@ -23,7 +23,8 @@
  *     the ciphertext moduli by their centred representative.
  *   - encryption ct = ([pk0 u + e0 + round(Q m / t)]_Q, [pk1 u + e1]_Q), u
  *     ternary, e0, e1 centred binomial (eta = 21), all drawn from ChaCha20
- *     (RFC 8439) streams: key = seed, nonce = (kind, id); see DESIGN notes.
+ *     (RFC 8439) streams: key = (seed low, seed high, 0, ..., 0), nonce =
+ *     (kind, id low, id high), block counter = word index / 16.
  *   - the rotate-and-accumulate loop of Algorithm 1 uses the Galois elements
  *     3^(n/4), 3^(n/8), ..., 3, then 2n-1 (row swap): log2 n rotations.
  *   - key switching: RNS digits [d]_{q_i}, one special prime P, rounded
