@@ -688,6 +688,34 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        # the same job one ciphertext at a time (tile = 1 pair): products, rotate-and-sum,
+        # bias and mask of the first 64 pairs, against the batched rate of the whole job;
+        # the masked pair ciphertexts must equal those of the tuned tile
+        npairs1 = 64
+        keep = ctx.tune_get("tile")
+        ref1 = ctx.empty_ct(npairs1)
+        wsr = ctx.workspace(P.native.WS_MATMUL_FAST, npairs1, wl.f, 1)
+        ctx.matmul_fast_pairs(keys, model, xct, rows, 0, npairs1, 0, out=ref1, ws=wsr)
+        ctx.tune_set("tile", 1)
+        o1 = ctx.empty_ct(npairs1)
+        ws1p = ctx.workspace(P.native.WS_MATMUL_FAST, npairs1, wl.f, 1)
+        ctx.matmul_fast_pairs(keys, model, xct, rows, 0, npairs1, 0, out=o1, ws=ws1p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.matmul_fast_pairs(keys, model, xct, rows, 0, npairs1, 0, out=o1, ws=ws1p)
+        torch.cuda.synchronize()
+        t_one = (time.perf_counter() - t0) / npairs1
+        ctx.tune_set("tile", keep)
+        assert torch.equal(o1, ref1), "one-at-a-time pair ciphertexts differ from the tuned tile's"
+        extras["one_ciphertext_at_a_time"] = {
+            "workload": f"batch_{rows}x{wl.f}x{classes}", "pairs_timed": npairs1,
+            "pairs_per_s": round(1.0 / t_one, 2), "inferences_per_s": round(1.0 / t_one / classes, 2),
+            "batched_server_pairs_per_s": round(server_rate * classes, 1),
+            "batched_over_one_at_a_time": round(server_rate * classes * t_one, 1)}
+        del ref1, wsr, o1, ws1p
+        torch.cuda.empty_cache()
+        log("one at a time", extras["one_ciphertext_at_a_time"])
+
         # single inference, 1 x 40,000: fast vs standard (encrypt + server + decrypt), and server only
         w1 = WL.single(f=args.features)
         X1 = torch.from_numpy(w1.X).cuda()
