@@ -677,6 +677,11 @@ def main():
                 "traffic": (counted_traffic(tuned["large"]["le_mac"], tuned["large"]["mac_mode"])
                             if lay_B == 4096 else None),
                 "avg_launch_ms": round(avg_ms, 4), "modmul_per_launch": per_launch}
+    if roofline["traffic"]:
+        # the same kernel against the HBM peak: counted bytes per launch over its live duration
+        rate = roofline["traffic"] / (avg_ms * 1e-3) / 1e9
+        roofline["traffic_gbps"] = round(rate, 1)
+        roofline["hbm_frac"] = round(rate / HBM_PEAK_GBPS, 4)
 
     # server-only rate (Algorithm 1 on resident ciphertexts)
     torch.cuda.synchronize()
