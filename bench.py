@@ -694,9 +694,9 @@ def main():
     extras = {}
     if not args.no_extras:
         # the same job one ciphertext at a time (tile = 1 pair): products, rotate-and-sum,
-        # bias and mask of the first 64 pairs, against the batched rate of the whole job;
+        # bias and mask of the first 64 pairs (or all, if fewer), against the batched rate of the whole job;
         # the masked pair ciphertexts must equal those of the tuned tile
-        npairs1 = 64
+        npairs1 = min(64, rows * classes)
         keep = ctx.tune_get("tile")
         ref1 = ctx.empty_ct(npairs1)
         wsr = ctx.workspace(P.native.WS_MATMUL_FAST, npairs1, wl.f, 1)
